@@ -1,0 +1,186 @@
+"""FP64 CPU oracle for the all-pairs GEMPE loss and gradient (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU-baseline leg
+of the benchmark, never by the library.  The arithmetic lives in ``gempe_oracle.c`` (plain
+C, double precision, brute force over all pairs); this module compiles it with gcc and
+marshals numpy arrays.  It imports nothing from the GPU package.
+
+Functions follow Sec. II-B (s+/-, dl+/-, Eq. 2) and Sec. II-C (Eqs. 3-5) of the paper;
+see the header comment of ``gempe_oracle.c`` for the exact definitions and readings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gempe_oracle.c")
+_LIB = os.path.join(_HERE, "libgempe_oracle.so")
+_lib = None
+
+LN2 = float(np.log(2.0))
+
+
+def compile_source(src: str, out: str) -> str:
+    """gcc -O2 -fopenmp build of an oracle source file into a shared library (IEEE math)."""
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+           src, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (always when force=True, else only if the source is newer)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        compile_source(_SRC, _LIB)
+    return _LIB
+
+
+def source_path() -> str:
+    return _SRC
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_pair.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                dp, dp, dp]
+    lib.oracle_pair.restype = None
+    lib.oracle_rows.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int, i64p, dp, dp, dp, i64p, dp, dp]
+    lib.oracle_rows.restype = None
+    lib.oracle_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
+                                     ctypes.c_double, dp, dp, i64p, dp]
+    lib.oracle_loss_grad.restype = None
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = _bind(_LIB)
+    return _lib
+
+
+def use_library(path):
+    """Point this module at another build of the oracle source (None: the default build).
+
+    Used by the tests that plant a mistake in a copy of the oracle source and check that
+    the pins catch it.
+    """
+    global _lib
+    _lib = None if path is None else _bind(path)
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    _load().oracle_set_num_threads(int(t))
+
+
+def pair(delta: float, is_edge: bool, mu: float = 1.5, sigma: float = 1.0):
+    """(dl, d dl/d delta, d^2 dl/d delta^2) of one vertex pair, dl in bits."""
+    lib = _load()
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib.oracle_pair(float(delta), int(bool(is_edge)), float(mu), float(sigma),
+                    ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def _graph_arrays(row_ptr, col_idx):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    return rp, ci
+
+
+def loss_grad(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0, want_grad=True,
+              want_row_loss=False):
+    """DL (bits), gradient (n x d), edge hits, optional per-vertex row loss; all FP64."""
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    loss = ctypes.c_double()
+    hits = ctypes.c_int64()
+    G = np.zeros((n, d), dtype=np.float64) if want_grad else None
+    RL = np.zeros(n, dtype=np.float64) if want_row_loss else None
+    lib.oracle_loss_grad(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64),
+                         _ptr(ci, ctypes.c_int32), float(mu), float(sigma), ctypes.byref(loss),
+                         _ptr(G, ctypes.c_double), ctypes.byref(hits), _ptr(RL, ctypes.c_double))
+    out = {"loss": loss.value, "edge_hits": hits.value}
+    if want_grad:
+        out["grad"] = G
+    if want_row_loss:
+        out["row_loss"] = RL
+    return out
+
+
+def rows(X, row_ptr, col_idx, rows_idx, mu: float = 1.5, sigma: float = 1.0, wm=False):
+    """Per-row quantities for a subset of rows, each row against all n vertices.
+
+    Returns grad (r x d), row_loss (r), upper_loss (r), upper_hits (r) and, with wm=True,
+    z (r) and y (r x d) of Eq. 5.
+    """
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    ri = np.ascontiguousarray(rows_idx, dtype=np.int64)
+    r = ri.shape[0]
+    G = np.zeros((r, d))
+    L = np.zeros(r)
+    U = np.zeros(r)
+    H = np.zeros(r, dtype=np.int64)
+    Z = np.zeros(r) if wm else None
+    Y = np.zeros((r, d)) if wm else None
+    lib.oracle_rows(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
+                    float(mu), float(sigma), r, _ptr(ri, ctypes.c_int64), _ptr(G, ctypes.c_double),
+                    _ptr(L, ctypes.c_double), _ptr(U, ctypes.c_double), _ptr(H, ctypes.c_int64),
+                    _ptr(Z, ctypes.c_double), _ptr(Y, ctypes.c_double))
+    out = {"grad": G, "row_loss": L, "upper_loss": U, "upper_hits": H}
+    if wm:
+        out["z"] = Z
+        out["y"] = Y
+    return out
+
+
+def gd_trajectory(X0, row_ptr, col_idx, iters: int, eta: float, mu: float = 1.5,
+                  sigma: float = 1.0):
+    """Fixed-step gradient descent X <- X - eta * G(X) in FP64.
+
+    Returns (loss history of length iters + 1, final X).  loss[k] is DL at X_k.
+    """
+    X = np.array(X0, dtype=np.float64)
+    hist = []
+    for k in range(iters + 1):
+        r = loss_grad(X, row_ptr, col_idx, mu, sigma)
+        hist.append(r["loss"])
+        if k < iters:
+            X = X - eta * r["grad"]
+    return np.array(hist), X
+
+
+def wm_update(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0):
+    """One weighted-majorization step (Eq. 5): x_i <- y_i / z_i for every vertex."""
+    n = np.asarray(X).shape[0]
+    r = rows(X, row_ptr, col_idx, np.arange(n), mu, sigma, wm=True)
+    return r["y"] / r["z"][:, None], r

@@ -1,0 +1,272 @@
+"""Pins for the FP64 oracle: checks against facts that do not come from the oracle itself.
+
+Each ``pin_*`` function raises AssertionError on failure.  The sources of truth are
+  * the paper's definitions of s+/-, dl+/- and Eq. 2 (Sec. II-B), evaluated literally
+    (the printed 1/2 -+ 1/2 erf form) in mpmath with >= 500 significant digits, with derivatives by
+    mpmath's high-precision numerical differentiation;
+  * scipy.special.log_ndtr as an independent library for log Phi;
+  * closed forms (delta = mu, two vertices, coincident points), identities
+    (s+ + s- = 1, reflection, the Eq. 5 rearrangement), invariances (translation,
+    rotation, torque, scale) and central finite differences of the oracle's own loss;
+  * brute force in pure Python + mpmath on tiny graphs.
+The same list runs against planted-mistake builds of the oracle in test_oracle_mutants.py.
+"""
+from __future__ import annotations
+
+import math
+
+import mpmath as mp
+import numpy as np
+from scipy.special import log_ndtr
+
+import oracle
+from paper_2011_03479_amd import synth
+
+MU, SIGMA = 1.5, 1.0
+
+
+# ----------------------------------------------------------------------------------------
+# literal evaluation of the paper's definitions (Sec. II-B) in high-precision arithmetic
+# ----------------------------------------------------------------------------------------
+
+def _digits(delta, mu, sigma):
+    """Working digits so that 1/2 -+ 1/2 erf keeps >= 500 significant digits at delta."""
+    t = (float(delta) - mu) / sigma
+    return 500 + int(0.22 * t * t)
+
+
+def mp_dl(delta, edge, mu=MU, sigma=SIGMA):
+    """dl+/- exactly as printed: -log2(1/2 -+ 1/2 erf((delta - mu)/(sqrt2 sigma)))."""
+    with mp.workdps(_digits(delta, mu, sigma)):
+        z = (mp.mpf(delta) - mp.mpf(mu)) / (mp.sqrt(2) * mp.mpf(sigma))
+        s = mp.mpf(1) / 2 - mp.erf(z) / 2 if edge else mp.mpf(1) / 2 + mp.erf(z) / 2
+        return -mp.log(s, 2)
+
+
+def mp_dl_derivs(delta, edge, mu=MU, sigma=SIGMA):
+    """(dl, dl', dl'') with central differences of step 1e-150 at >= 500 digits."""
+    with mp.workdps(_digits(delta, mu, sigma)):
+        f = lambda x: mp_dl(x, edge, mu, sigma)  # noqa: E731
+        x = mp.mpf(delta)
+        h = mp.mpf(10) ** -150
+        return f(x), mp.diff(f, x, 1, h=h), mp.diff(f, x, 2, h=h)
+
+
+def close(a, b, rel=1e-12, abs_=1e-300):
+    a = float(a)
+    b = float(b)
+    return abs(a - b) <= rel * abs(b) + abs_
+
+
+# ----------------------------------------------------------------------------------------
+# pins on the pair function
+# ----------------------------------------------------------------------------------------
+
+PAIR_GRID = [0.0, 0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.5, 6.0, 10.0, 20.0, 30.0, 36.4, 36.6, 40.0, 60.0]
+PARAMS = [(1.5, 1.0), (2.0, 0.5), (0.7, 1.7)]
+
+
+def pin_pair_vs_mpmath():
+    for mu, sigma in PARAMS:
+        for delta in PAIR_GRID:
+            if abs(delta - mu) / sigma > 60.0:
+                continue
+            for edge in (True, False):
+                dl, d1, d2 = oracle.pair(delta, edge, mu, sigma)
+                rdl, rd1, rd2 = mp_dl_derivs(delta, edge, mu, sigma)
+                assert close(dl, rdl, 1e-12), (mu, sigma, delta, edge, dl, rdl)
+                assert close(d1, rd1, 1e-10), (mu, sigma, delta, edge, d1, rd1)
+                assert close(d2, rd2, 1e-8), (mu, sigma, delta, edge, d2, rd2)
+
+
+def pin_pair_vs_scipy():
+    """-log2 Phi(tau) against scipy's log_ndtr over edge and non-edge ranges."""
+    for mu, sigma in PARAMS:
+        for edge in (True, False):
+            deltas = np.linspace(0.0, mu + 60 * sigma, 1201)
+            for delta in deltas:
+                a = -1.0 if edge else 1.0
+                tau = a * (delta - mu) / sigma
+                dl, d1, _ = oracle.pair(delta, edge, mu, sigma)
+                ref = -log_ndtr(tau) / math.log(2)
+                # a far tail is as exact as exp(-tau^2/2) of a rounded tau: ~tau^2 ulp
+                rel = 1e-14 * (4.0 + tau * tau)
+                assert close(dl, ref, rel, 1e-300), (edge, delta, dl, ref)
+                # R = phi/Phi from the same library: d1 = -(a/sigma) R / ln2
+                logR = -0.5 * tau * tau - 0.5 * math.log(2 * math.pi) - log_ndtr(tau)
+                ref1 = -(a / sigma) * math.exp(logR) / math.log(2)
+                assert close(d1, ref1, 4 * rel, 1e-300), (edge, delta, d1, ref1)
+
+
+def pin_pair_closed_forms():
+    # delta = mu: s+ = s- = 1/2, so dl = 1 bit; slope +-sqrt(2/pi)/(sigma ln 2)
+    for mu, sigma in PARAMS:
+        for edge in (True, False):
+            dl, d1, _ = oracle.pair(mu, edge, mu, sigma)
+            assert close(dl, 1.0, 1e-15)
+            slope = math.sqrt(2 / math.pi) / (sigma * math.log(2))
+            assert close(d1, slope if edge else -slope, 1e-14)
+    # reflection: dl+(mu + D) = dl-(mu - D), d dl+(mu + D) = -d dl-(mu - D)
+    for D in (0.3, 1.0, 1.5):
+        a = oracle.pair(MU + D, True)
+        b = oracle.pair(MU - D, False)
+        assert close(a[0], b[0], 1e-14) and close(a[1], -b[1], 1e-13)
+    # s+ + s- = 1 (the two probabilities of Sec. II-B are complementary)
+    for delta in (0.0, 0.7, 1.5, 2.9, 5.0):
+        p = 2.0 ** -oracle.pair(delta, True)[0] + 2.0 ** -oracle.pair(delta, False)[0]
+        assert close(p, 1.0, 1e-14)
+
+
+# ----------------------------------------------------------------------------------------
+# pins on the whole-graph loss / gradient
+# ----------------------------------------------------------------------------------------
+
+def _graph_from_edges(n, edges):
+    u = np.array([e[0] for e in edges], dtype=np.int64)
+    v = np.array([e[1] for e in edges], dtype=np.int64)
+    return synth.csr_from_edges(n, u, v)
+
+
+def pin_two_vertices():
+    X = np.array([[0.0, 0.0], [3.0, 4.0]])
+    for edge in (True, False):
+        g = _graph_from_edges(2, [(0, 1)] if edge else [])
+        r = oracle.loss_grad(X, g.row_ptr, g.col_idx)
+        dl, d1, _ = mp_dl_derivs(5.0, edge)
+        assert close(r["loss"], dl, 1e-13)
+        g1 = float(d1) * (X[0] - X[1]) / 5.0
+        assert np.allclose(r["grad"][0], g1, rtol=1e-10, atol=0)
+        assert np.allclose(r["grad"][1], -g1, rtol=1e-10, atol=0)
+        assert r["edge_hits"] == (1 if edge else 0)
+
+
+def pin_coincident_points():
+    g = synth.erdos_renyi(9, 3.0, seed=11)
+    X = np.full((9, 3), 0.37)
+    r = oracle.loss_grad(X, g.row_ptr, g.col_idx)
+    N = 9 * 8 // 2
+    ref = g.m * float(mp_dl(0.0, True)) + (N - g.m) * float(mp_dl(0.0, False))
+    assert close(r["loss"], ref, 1e-13)
+    assert np.all(r["grad"] == 0.0)
+    assert r["edge_hits"] == g.m
+
+
+def pin_brute_force_tiny():
+    """Pure Python + mpmath over all pairs of a 6-vertex graph (loss, gradient, hits)."""
+    rng = np.random.default_rng(5)
+    n, d = 6, 2
+    X = rng.standard_normal((n, d))
+    edges = [(0, 1), (1, 2), (2, 5), (3, 4), (0, 5)]
+    g = _graph_from_edges(n, edges)
+    E = set(edges) | {(b, a) for a, b in edges}
+    loss = mp.mpf(0)
+    grad = [[mp.mpf(0)] * d for _ in range(n)]
+    hits = 0
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            diff = [mp.mpf(float(X[i, k])) - mp.mpf(float(X[j, k])) for k in range(d)]
+            delta = mp.sqrt(sum(t * t for t in diff))
+            dl, d1, _ = mp_dl_derivs(delta, (i, j) in E)
+            if i < j:
+                loss += dl
+                hits += (i, j) in E
+            for k in range(d):
+                grad[i][k] += d1 * diff[k] / delta
+    r = oracle.loss_grad(X, g.row_ptr, g.col_idx)
+    assert close(r["loss"], loss, 1e-13)
+    assert np.allclose(r["grad"], np.array([[float(v) for v in row] for row in grad]),
+                       rtol=1e-10, atol=1e-14)
+    assert r["edge_hits"] == hits == len(edges)
+
+
+def pin_finite_differences():
+    for n, d, seed in ((8, 1, 1), (12, 2, 2), (10, 3, 3), (9, 8, 4)):
+        g = synth.erdos_renyi(n, 0.35 * (n - 1), seed=seed)
+        rng = np.random.default_rng(100 + seed)
+        X = rng.standard_normal((n, d)) * 1.3
+        G = oracle.loss_grad(X, g.row_ptr, g.col_idx)["grad"]
+        h = 1e-6
+        for i in range(n):
+            for k in range(d):
+                Xp = X.copy()
+                Xm = X.copy()
+                Xp[i, k] += h
+                Xm[i, k] -= h
+                fd = (oracle.loss_grad(Xp, g.row_ptr, g.col_idx, want_grad=False)["loss"]
+                      - oracle.loss_grad(Xm, g.row_ptr, g.col_idx, want_grad=False)["loss"]) / (2 * h)
+                assert abs(fd - G[i, k]) <= 1e-6 * max(1.0, abs(G[i, k])), (n, d, i, k, fd, G[i, k])
+
+
+def pin_invariances():
+    rng = np.random.default_rng(21)
+    n, d = 40, 3
+    g = synth.erdos_renyi(n, 5.0, seed=21)
+    X = rng.standard_normal((n, d))
+    r = oracle.loss_grad(X, g.row_ptr, g.col_idx)
+    G = r["grad"]
+    scale = np.abs(G).sum()
+    # translation: the loss only sees differences, so the gradients sum to zero
+    assert np.all(np.abs(G.sum(axis=0)) <= 1e-12 * scale)
+    rt = oracle.loss_grad(X + np.array([3.0, -2.0, 0.5]), g.row_ptr, g.col_idx)
+    assert close(rt["loss"], r["loss"], 1e-12)
+    # rotation: DL(XQ) = DL(X), G(XQ) = G(X) Q
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    rq = oracle.loss_grad(X @ Q, g.row_ptr, g.col_idx)
+    assert close(rq["loss"], r["loss"], 1e-12)
+    assert np.allclose(rq["grad"], G @ Q, rtol=0, atol=1e-11 * np.abs(G).max())
+    # no torque: sum_i x_i g_i^T is symmetric
+    T = X.T @ G
+    assert np.allclose(T, T.T, rtol=0, atol=1e-11 * np.abs(T).max())
+    # scale covariance: DL(cX; c mu, c sigma) = DL(X; mu, sigma), G scales by 1/c
+    c = 2.5
+    rs = oracle.loss_grad(c * X, g.row_ptr, g.col_idx, mu=c * MU, sigma=c * SIGMA)
+    assert close(rs["loss"], r["loss"], 1e-12)
+    assert np.allclose(rs["grad"], G / c, rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def pin_edge_hits_and_rows():
+    g = synth.chung_lu(300, 8.0, 2.5, seed=7)
+    X = synth.init_embedding(300, 2, 1007)
+    r = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_row_loss=True)
+    assert r["edge_hits"] == g.m
+    # the row losses count every pair twice, the loss once
+    assert close(r["row_loss"].sum(), 2 * r["loss"], 1e-12)
+    sub = np.array([0, 17, 299, 123])
+    rr = oracle.rows(X, g.row_ptr, g.col_idx, sub)
+    assert np.allclose(rr["grad"], r["grad"][sub], rtol=1e-13, atol=0)
+    assert np.allclose(rr["row_loss"], r["row_loss"][sub], rtol=1e-13, atol=0)
+    assert int(np.sum(np.diff(g.row_ptr)[sub])) >= int(rr["upper_hits"].sum())
+
+
+def pin_wm_identity():
+    """Eq. 5 with derivative-matched parabolas equals x_i - g_i / (2 z_i), z_i > 0."""
+    rng = np.random.default_rng(31)
+    n, d = 25, 2
+    g = synth.erdos_renyi(n, 4.0, seed=31)
+    X = rng.standard_normal((n, d))
+    Xn, r = oracle.wm_update(X, g.row_ptr, g.col_idx)
+    G = oracle.loss_grad(X, g.row_ptr, g.col_idx)["grad"]
+    assert np.all(r["z"] > 0)
+    assert np.allclose(Xn, X - G / (2 * r["z"][:, None]), rtol=0, atol=1e-12)
+    # the parabola weight is half the second derivative (checked at the pair level)
+    for delta in (0.4, 1.5, 3.0):
+        for edge in (True, False):
+            _, _, d2 = oracle.pair(delta, edge)
+            _, _, rd2 = mp_dl_derivs(delta, edge)
+            assert close(d2, rd2, 1e-8)
+
+
+ALL_PINS = [
+    pin_pair_vs_mpmath,
+    pin_pair_vs_scipy,
+    pin_pair_closed_forms,
+    pin_two_vertices,
+    pin_coincident_points,
+    pin_brute_force_tiny,
+    pin_finite_differences,
+    pin_invariances,
+    pin_edge_hits_and_rows,
+    pin_wm_identity,
+]

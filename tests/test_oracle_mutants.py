@@ -1,0 +1,51 @@
+"""Plant plausible mistakes in a copy of the oracle source; the pins must catch each one.
+
+Every mutant is a text replacement in a temporary copy of oracle/gempe_oracle.c, built with
+the same flags.  A mutant that no pin rejects would mean the pins cannot tell that mistake
+from the paper's definitions, so the test fails.
+"""
+import os
+
+import pytest
+
+import oracle
+import pins
+
+MUTANTS = {
+    "edge_sign_swapped": ("double a = is_edge ? -1.0 : 1.0;", "double a = is_edge ? 1.0 : -1.0;"),
+    "slope_missing_sigma": ("if (d1) *d1 = -(a / sigma) * R / ORACLE_LN2;",
+                            "if (d1) *d1 = -a * R / ORACLE_LN2;"),
+    "natural_log_bits": ("if (dl) *dl = -log_Phi(tau) / ORACLE_LN2;", "if (dl) *dl = -log_Phi(tau);"),
+    "gradient_sign": ("gi[k] += c * (xi[k] - xj[k]);", "gi[k] += c * (xj[k] - xi[k]);"),
+    "gradient_not_unit": ("double c = (delta > 0.0) ? d1 / delta : 0.0;", "double c = d1;"),
+    "loss_both_triangles": ("if (j > i) {", "if (j != i) {"),
+    "membership_wrong_index": ("int edge = flag[j] != 0;", "int edge = flag[i] != 0;"),
+    "erfc_missing_sqrt2": ("return log1p(-0.5 * erfc(t / ORACLE_SQRT2));",
+                           "return log1p(-0.5 * erfc(t));"),
+    "tail_series_sign": ("q * (3.0 + q * (-15.0", "q * (3.0 + q * (15.0"),
+    "tail_log_term": ("- log(-t) - ORACLE_LOG_SQRT_2PI", "+ log(-t) - ORACLE_LOG_SQRT_2PI"),
+    "second_derivative_sign": ("(tau * R + R * R)", "(tau * R - R * R)"),
+    "distance_not_squared": ("r2 += t * t;", "r2 += fabs(t);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(tmp_path, oracle_mod, name):
+    src = open(oracle.source_path()).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation anchor not unique for {name}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = oracle.compile_source(str(path), str(tmp_path / f"libmutant_{name}.so"))
+    caught = []
+    oracle.use_library(lib)
+    try:
+        for pin in pins.ALL_PINS:
+            try:
+                pin()
+            except AssertionError:
+                caught.append(pin.__name__)
+                break
+    finally:
+        oracle.use_library(None)
+    assert caught, f"no pin rejects mutant {name}"
