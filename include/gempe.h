@@ -1,0 +1,167 @@
+/*
+ * gempe.h -- C ABI of the MI355X (gfx950) library for the all-pairs GEMPE coding cost.
+ *
+ * GEMPE (graph embedding by minimising the predictive entropy, Boehm and Plant) scores an
+ * embedding x_1..x_n in R^d of a graph G = (V, E) by the number of bits needed to code
+ * the upper triangle of the adjacency matrix when the probability that (i, j) is an edge
+ * is a sigmoid of the distance delta_ij = |x_i - x_j| (Sec. II-B, Eq. 2):
+ *
+ *   s+(delta) = Phi(-(delta - mu)/sigma),  s-(delta) = Phi((delta - mu)/sigma)
+ *   dl(i,j)   = -log2 s+(delta_ij) if (i,j) in E, -log2 s-(delta_ij) otherwise
+ *   DL        = sum_{i<j} dl(i,j)  [bits],   PE = DL / N,  N = n(n-1)/2
+ *
+ * with Phi the standard normal CDF (1/2 -+ 1/2 erf(z) of the paper).  The library
+ * evaluates DL and its gradient g_i = dDL/dx_i over ALL n(n-1)/2 vertex pairs (the
+ * "non-sampling version" of Sec. III-C), at fixed mu and sigma, and runs fixed-step
+ * gradient descent on it.  The contribution of a coincident pair (delta = 0) to the
+ * gradient is 0, the convention Eq. 5 uses for s_ij.
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers unless marked [host].  The caller owns all memory
+ *     passed in; the library owns what a graph handle allocates in gempe_graph_create.
+ *   - Matrices are row-major: X and grad are n x d float32, vertex i at X + i*d.
+ *   - Vertex ids are 0-based; col_idx is int32 (n < 2^31), row_ptr is int64.
+ *   - No exceptions cross the ABI.  Every call returns a gempe_status; argument errors
+ *     are detected synchronously on the host before anything is enqueued.
+ *     gempe_last_error() returns a thread-local message describing the last failure.
+ *   - Asynchronous calls enqueue work on `stream` (0 = the null stream) and return
+ *     immediately; results are valid once the stream reaches them.
+ *   - The hot-path calls allocate no device memory: scratch comes from a caller-provided
+ *     workspace of at least gempe_workspace_bytes() bytes (256-byte aligned).
+ *   - Calls on one graph handle may run concurrently on different streams only if they
+ *     use disjoint workspaces and outputs.
+ */
+#ifndef GEMPE_H
+#define GEMPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gempe_status {
+    GEMPE_OK = 0,
+    GEMPE_ERR_ARG = -1,          /* invalid argument (sizes, null pointers, parameters)   */
+    GEMPE_ERR_GRAPH = -2,        /* CSR not a simple undirected graph (see graph_create)   */
+    GEMPE_ERR_NOMEM = -3,        /* workspace too small, or a set-up allocation failed     */
+    GEMPE_ERR_HIP = -4,          /* a HIP runtime call failed                              */
+    GEMPE_ERR_NUMERIC = -5,      /* non-finite loss or coordinates detected on the device  */
+    GEMPE_ERR_UNSUPPORTED = -6,  /* valid request this build does not implement            */
+    GEMPE_ERR_TIMEOUT = -7       /* a device-side wait exceeded its bound                  */
+} gempe_status;
+
+/* Arithmetic of the all-pairs sweep. */
+typedef enum gempe_precision {
+    GEMPE_FP32 = 0,      /* every pair in FP32 (1 <= d <= 128)                              */
+    GEMPE_BF16_GRAM = 1  /* d >= 16, d % 16 == 0: distances screened by a BF16 MFMA Gram
+                            tile with FP32 accumulation; edges and pairs whose screened
+                            distance is below mu + near_k*sigma + margin are recomputed
+                            exactly in FP32, the remaining far non-edges contribute 0 */
+} gempe_precision;
+
+/* Flags (gempe_params.flags). */
+#define GEMPE_F_NONE 0u
+
+typedef struct gempe_params {
+    double mu;          /* sigmoid position; the paper fixes mu = 1.5 (Sec. III-F)         */
+    double sigma;       /* sigmoid slope, > 0; the paper starts from sigma = 1 (Fig. algo)  */
+    int32_t precision;  /* gempe_precision                                                  */
+    int32_t reserved0;  /* must be 0                                                        */
+    double near_k;      /* BF16_GRAM only: exact-recompute cut-off in sigmas (default 9)    */
+    uint32_t flags;     /* GEMPE_F_* (currently none)                                       */
+    uint32_t reserved1; /* must be 0                                                        */
+} gempe_params;
+
+/* Fills *p with mu = 1.5, sigma = 1, FP32, near_k = 9, no flags. [host] */
+void gempe_params_default(gempe_params *p);
+
+typedef struct gempe_graph_s *gempe_graph;
+
+/*
+ * Uploads and validates a graph (Sec. II-A: n vertices, m undirected, unweighted,
+ * unlabeled edges) given as symmetric CSR on the device:
+ *   row_ptr : int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx : int32[nnz], nnz = 2m; each row sorted strictly ascending, no self-loops,
+ *             every (i, j) present together with (j, i)
+ * The library copies the CSR (the caller may free its buffers after return) and builds
+ * an exact open-addressing hash of the m undirected edges (64-bit keys, capacity the
+ * power of two >= 2m, load factor <= 0.5) in device memory.  Synchronous: returns after
+ * validation; GEMPE_ERR_GRAPH if the CSR violates any rule above.  *out [host] receives
+ * the handle; n >= 1, nnz >= 0.
+ */
+gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                const int32_t *col_idx, hipStream_t stream, gempe_graph *out);
+
+/* Releases the handle and its device memory (synchronises the device first). */
+gempe_status gempe_graph_destroy(gempe_graph g);
+
+int32_t gempe_graph_num_vertices(gempe_graph g); /* n, or -1 for a null handle */
+int64_t gempe_graph_num_edges(gempe_graph g);    /* m (undirected), or -1      */
+
+/*
+ * Batch membership query against the exact edge hash: out[k] = 1 if {qi[k], qj[k]} is an
+ * edge, else 0, for k < q.  qi, qj: int32[q] in [0, n) (out-of-range ids give 0);
+ * out: uint8[q].  Asynchronous.
+ */
+gempe_status gempe_has_edge(gempe_graph g, int64_t q, const int32_t *qi, const int32_t *qj,
+                            uint8_t *out, hipStream_t stream);
+
+/* Bytes of workspace needed by gempe_loss_grad / gempe_step / gempe_embed for this
+ * graph, dimension and parameters (0 on invalid arguments). [host] */
+size_t gempe_workspace_bytes(gempe_graph g, int32_t d, const gempe_params *p);
+
+/*
+ * All-pairs loss and gradient at X (Eq. 2 at fixed mu, sigma; gradient of DL):
+ *   X         : float32[n*d]                      (input)
+ *   grad      : float32[n*d] or NULL              g_i = dDL/dx_i
+ *   loss      : float64[1]                        DL in bits (PE = DL / N)
+ *   edge_hits : int64[1] or NULL                  number of pairs i<j scored as edges;
+ *                                                 equals m when membership is exact
+ *   row_loss  : float32[n] or NULL                L_i = sum_{j != i} dl(i,j)
+ *   ws        : workspace of ws_bytes >= gempe_workspace_bytes(g, d, p)
+ * FP32 arithmetic per pair; the loss is summed in FP32 per tile and in FP64 across
+ * tiles in a fixed order (deterministic).  The gradient is accumulated with FP32
+ * atomics across tiles (order of summation varies between runs).  Asynchronous.
+ */
+gempe_status gempe_loss_grad(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
+                             int64_t *edge_hits, float *row_loss, void *ws, size_t ws_bytes,
+                             const gempe_params *p, hipStream_t stream);
+
+/*
+ * One fixed-step gradient-descent step X <- X - eta * grad DL(X), in place.
+ *   loss_before : float64[1] or NULL, receives DL at the X on entry
+ * eta > 0 and finite.  Asynchronous.
+ */
+gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta, double *loss_before,
+                        void *ws, size_t ws_bytes, const gempe_params *p, hipStream_t stream);
+
+/*
+ * iters steps of fixed-step gradient descent (the repeat loop of the paper's driver,
+ * with the weighted-majorization update replaced by X <- X - eta * grad DL):
+ *   X         : float32[n*d], initial coordinates in, final coordinates out
+ *   loss_hist : float64[iters+1] or NULL; loss_hist[k] = DL(X_k), k = 0..iters
+ *               (computing loss_hist[iters] costs one extra loss-only sweep)
+ * Runs as one persistent launch when the graph is small enough for one grid-wide
+ * barrier per iteration to pay, else as a sequence of launches.  Synchronises the
+ * stream once at the end to read the device status word: returns GEMPE_ERR_NUMERIC if
+ * a non-finite loss appeared, GEMPE_ERR_TIMEOUT if a grid barrier wait ran out.
+ */
+gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, float eta,
+                         double *loss_hist, void *ws, size_t ws_bytes, const gempe_params *p,
+                         hipStream_t stream);
+
+/* Static description of a status code. [host] */
+const char *gempe_status_string(gempe_status s);
+
+/* Thread-local description of the last error raised by a call on this thread. [host] */
+const char *gempe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEMPE_H */

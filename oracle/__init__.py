@@ -54,10 +54,10 @@ def _bind(path: str):
                                 dp, dp, dp]
     lib.oracle_pair.restype = None
     lib.oracle_rows.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
-                                ctypes.c_double, ctypes.c_int, i64p, dp, dp, dp, i64p, dp, dp]
+                                ctypes.c_double, ctypes.c_int, i64p, dp, dp, dp, i64p, dp, dp, dp]
     lib.oracle_rows.restype = None
     lib.oracle_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
-                                     ctypes.c_double, dp, dp, i64p, dp]
+                                     ctypes.c_double, dp, dp, i64p, dp, dp]
     lib.oracle_loss_grad.restype = None
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -113,8 +113,9 @@ def _graph_arrays(row_ptr, col_idx):
 
 
 def loss_grad(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0, want_grad=True,
-              want_row_loss=False):
-    """DL (bits), gradient (n x d), edge hits, optional per-vertex row loss; all FP64."""
+              want_row_loss=False, want_abs_slope=False):
+    """DL (bits), gradient (n x d), edge hits, optional per-vertex row loss and
+    A_i = sum_j |d dl_ij / d delta| (the magnitude of the terms that cancel in g_i); FP64."""
     lib = _load()
     Xd = np.ascontiguousarray(X, dtype=np.float64)
     n, d = Xd.shape
@@ -123,22 +124,26 @@ def loss_grad(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0, want_gra
     hits = ctypes.c_int64()
     G = np.zeros((n, d), dtype=np.float64) if want_grad else None
     RL = np.zeros(n, dtype=np.float64) if want_row_loss else None
+    AS = np.zeros(n, dtype=np.float64) if want_abs_slope else None
     lib.oracle_loss_grad(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64),
                          _ptr(ci, ctypes.c_int32), float(mu), float(sigma), ctypes.byref(loss),
-                         _ptr(G, ctypes.c_double), ctypes.byref(hits), _ptr(RL, ctypes.c_double))
+                         _ptr(G, ctypes.c_double), ctypes.byref(hits), _ptr(RL, ctypes.c_double),
+                         _ptr(AS, ctypes.c_double))
     out = {"loss": loss.value, "edge_hits": hits.value}
     if want_grad:
         out["grad"] = G
     if want_row_loss:
         out["row_loss"] = RL
+    if want_abs_slope:
+        out["abs_slope"] = AS
     return out
 
 
 def rows(X, row_ptr, col_idx, rows_idx, mu: float = 1.5, sigma: float = 1.0, wm=False):
     """Per-row quantities for a subset of rows, each row against all n vertices.
 
-    Returns grad (r x d), row_loss (r), upper_loss (r), upper_hits (r) and, with wm=True,
-    z (r) and y (r x d) of Eq. 5.
+    Returns grad (r x d), row_loss (r), upper_loss (r), upper_hits (r), abs_slope (r) and,
+    with wm=True, z (r) and y (r x d) of Eq. 5.
     """
     lib = _load()
     Xd = np.ascontiguousarray(X, dtype=np.float64)
@@ -152,11 +157,12 @@ def rows(X, row_ptr, col_idx, rows_idx, mu: float = 1.5, sigma: float = 1.0, wm=
     H = np.zeros(r, dtype=np.int64)
     Z = np.zeros(r) if wm else None
     Y = np.zeros((r, d)) if wm else None
+    AS = np.zeros(r)
     lib.oracle_rows(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
                     float(mu), float(sigma), r, _ptr(ri, ctypes.c_int64), _ptr(G, ctypes.c_double),
                     _ptr(L, ctypes.c_double), _ptr(U, ctypes.c_double), _ptr(H, ctypes.c_int64),
-                    _ptr(Z, ctypes.c_double), _ptr(Y, ctypes.c_double))
-    out = {"grad": G, "row_loss": L, "upper_loss": U, "upper_hits": H}
+                    _ptr(Z, ctypes.c_double), _ptr(Y, ctypes.c_double), _ptr(AS, ctypes.c_double))
+    out = {"grad": G, "row_loss": L, "upper_loss": U, "upper_hits": H, "abs_slope": AS}
     if wm:
         out["z"] = Z
         out["y"] = Y

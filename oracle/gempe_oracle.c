@@ -106,11 +106,13 @@ static void mark_row(const int64_t *row_ptr, const int32_t *col_idx, int i, unsi
  *   upper_hits: nrows output, number of edges (i, j) with j > i recognised; may be NULL
  *   zsum      : nrows output, z_i = sum_{j != i} w_ij (Eq. 5 denominator); may be NULL
  *   ysum      : nrows x d output, y_i = sum_{j != i} w_ij (x_j + s_ij (x_i - x_j)); may be NULL
+ *   abs_slope : nrows output, A_i = sum_{j != i} |d dl(i,j) / d delta| (the scale of the terms
+ *               that cancel in g_i; used for gradient tolerances); may be NULL
  */
 void oracle_rows(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
                  double mu, double sigma, int nrows, const int64_t *rows, double *grad,
                  double *row_loss, double *upper_loss, int64_t *upper_hits, double *zsum,
-                 double *ysum) {
+                 double *ysum, double *abs_slope) {
     if (rows == NULL) nrows = n;
 #pragma omp parallel
     {
@@ -122,7 +124,7 @@ void oracle_rows(int n, int d, const double *X, const int64_t *row_ptr, const in
             int i = rows ? (int)rows[r] : r;
             const double *xi = X + (size_t)i * d;
             mark_row(row_ptr, col_idx, i, flag, 1);
-            double L = 0.0, U = 0.0, z = 0.0;
+            double L = 0.0, U = 0.0, z = 0.0, A = 0.0;
             int64_t hits = 0;
             for (int k = 0; k < d; ++k) gi[k] = 0.0, yi[k] = 0.0;
             for (int j = 0; j < n; ++j) {
@@ -138,6 +140,7 @@ void oracle_rows(int n, int d, const double *X, const int64_t *row_ptr, const in
                 double dl, d1, d2;
                 oracle_pair(delta, edge, mu, sigma, &dl, &d1, &d2);
                 L += dl;
+                A += fabs(d1);
                 if (j > i) {
                     U += dl;
                     hits += edge;
@@ -160,6 +163,7 @@ void oracle_rows(int n, int d, const double *X, const int64_t *row_ptr, const in
             if (upper_loss) upper_loss[r] = U;
             if (upper_hits) upper_hits[r] = hits;
             if (zsum) zsum[r] = z;
+            if (abs_slope) abs_slope[r] = A;
             if (ysum)
                 for (int k = 0; k < d; ++k) ysum[(size_t)r * d + k] = yi[k];
         }
@@ -175,13 +179,15 @@ void oracle_rows(int n, int d, const double *X, const int64_t *row_ptr, const in
  *   grad      : n x d, may be NULL
  *   edge_hits : number of pairs i<j recognised as edges (must equal m)
  *   row_loss  : n, L_i = sum_{j != i} dl(i, j); may be NULL
+ *   abs_slope : n, A_i = sum_{j != i} |d dl(i, j) / d delta|; may be NULL
  */
 void oracle_loss_grad(int n, int d, const double *X, const int64_t *row_ptr,
                       const int32_t *col_idx, double mu, double sigma, double *loss, double *grad,
-                      int64_t *edge_hits, double *row_loss) {
+                      int64_t *edge_hits, double *row_loss, double *abs_slope) {
     double *U = (double *)malloc(sizeof(double) * (size_t)n);
     int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-    oracle_rows(n, d, X, row_ptr, col_idx, mu, sigma, n, NULL, grad, row_loss, U, H, NULL, NULL);
+    oracle_rows(n, d, X, row_ptr, col_idx, mu, sigma, n, NULL, grad, row_loss, U, H, NULL, NULL,
+                abs_slope);
     double total = 0.0;
     int64_t hits = 0;
     for (int i = 0; i < n; ++i) total += U[i], hits += H[i];

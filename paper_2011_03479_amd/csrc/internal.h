@@ -1,0 +1,123 @@
+// Internal declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/gempe.h"
+
+// Device-side status bits (gempe_graph_s::status_dev and the embed status word).
+enum : unsigned {
+    kStatusNonFinite = 1u,    // a loss partial or a coordinate was NaN/Inf
+    kStatusTimeout = 2u,      // a grid-barrier wait ran out of its spin budget
+    kStatusBadRowPtr = 4u,    // row_ptr not monotone / out of [0, nnz]
+    kStatusBadCol = 8u,       // column id out of range or a self-loop
+    kStatusUnsorted = 16u,    // a row not strictly ascending (duplicate or unsorted)
+    kStatusAsymmetric = 32u,  // (i, j) present without (j, i)
+    kStatusHashFull = 64u,    // hash insertion found no free slot (cannot happen at LF <= 0.5)
+};
+
+struct gempe_graph_s {
+    int32_t n = 0;
+    int64_t nnz = 0;     // directed entries, 2m
+    int64_t m = 0;       // undirected edges
+    int device = 0;
+    int64_t *row_ptr = nullptr;  // device copy, int64[n+1]
+    int32_t *col_idx = nullptr;  // device copy, int32[nnz]
+    int32_t *coo_row = nullptr;  // device, row id of every CSR entry, int32[nnz]
+    unsigned long long *hash = nullptr;  // device, open addressing, capacity hash_cap
+    uint64_t hash_cap = 0;       // power of two >= 2m (>= 2)
+    unsigned *status_dev = nullptr;  // device words: [0] graph validation, [1] counters
+};
+
+// Empty slot marker of the edge hash (keys are (min << 32) | max with min < max < 2^31).
+constexpr unsigned long long kHashEmpty = ~0ull;
+
+// Thread-local error text (api.hip).
+void gempe_set_error(const std::string &msg);
+gempe_status gempe_fail(gempe_status s, const std::string &msg);
+
+#define GEMPE_HIP_TRY(expr)                                                            \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            return gempe_fail(GEMPE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// 64-bit finaliser of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): a bijective mix
+// so that linear probing sees well-spread home slots for structured (i, j) keys.
+__host__ __device__ inline unsigned long long gempe_mix64(unsigned long long x) {
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__host__ __device__ inline unsigned long long gempe_edge_key(int a, int b) {
+    unsigned lo = (unsigned)(a < b ? a : b), hi = (unsigned)(a < b ? b : a);
+    return ((unsigned long long)lo << 32) | hi;
+}
+
+// Device-side exact membership probe (linear probing; the table is at most half full, so
+// an empty slot ends every search; the loop bound is a safety net only).
+__device__ inline bool gempe_hash_contains(const unsigned long long *__restrict__ table,
+                                           unsigned long long cap, unsigned long long key) {
+    unsigned long long mask = cap - 1, s = gempe_mix64(key) & mask;
+    for (unsigned long long probe = 0; probe < cap; ++probe) {
+        unsigned long long v = table[s];
+        if (v == key) return true;
+        if (v == kHashEmpty) return false;
+        s = (s + 1) & mask;
+    }
+    return false;
+}
+
+// ------------------------------------------------------------------------------------
+// Workspace layout for the loss/gradient and step/embed calls.
+// ------------------------------------------------------------------------------------
+struct SweepPlan {
+    int D = 0;          // padded compile-time dimension (1,2,3,4,8,16,32,64,128)
+    int R = 1;          // rows per lane
+    int W = 1;          // waves per workgroup sharing a column block
+    int T = 64;         // super-tile edge (rows = columns) = 64 * R * W
+    int nt = 0;         // tiles per side
+    long long items = 0;  // upper-triangle super tiles nt (nt + 1) / 2
+    long long grid = 0;   // workgroups launched (multiple of 8, >= items)
+    int edge_blocks = 0;  // blocks of the exact edge pass
+    long long partials = 0;  // float loss partials: items + edge_blocks
+};
+
+struct WsLayout {
+    size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, ...
+    size_t partials = 0;  // float[plan.partials]
+    size_t gbuf = 0;      // float[n*d] gradient scratch for gempe_step/gempe_embed
+    size_t xbuf = 0;      // float[2*n*d] embed: double-buffered coordinates
+    size_t gring = 0;     // float[3*n*d] embed: three gradient slots
+    size_t ppart = 0;     // float[2*plan.partials] embed: double-buffered loss partials
+    size_t barrier = 0;   // 256 B: grid barrier counter + generation
+    size_t total = 0;
+};
+
+SweepPlan gempe_make_plan(const gempe_graph_s *g, int d);
+WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
+
+// Kernel launchers (sweep.hip).
+struct PairParamsHost {
+    float mu, inv_sigma, d1_scale;  // d1_scale = -1 / (sigma ln 2)
+};
+PairParamsHost gempe_pair_params(const gempe_params *p);
+
+hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan,
+                                  const float *X, float *grad, float *row_loss, float *partials,
+                                  unsigned char *counters, double *loss, int64_t *hits_out,
+                                  const PairParamsHost &pp, hipStream_t s, bool clear_status);
+hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
+hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan,
+                                         float *X, int iters, float eta, double *loss_hist,
+                                         const WsLayout &L, unsigned char *ws,
+                                         const PairParamsHost &pp, hipStream_t s, bool *used);

@@ -1,0 +1,269 @@
+"""ctypes binding of libgempe.so (include/gempe.h), argument marshalling only.
+
+Every call here forwards to the HIP library; nothing is computed in Python.  PyTorch is
+used for device memory (tensors' data pointers) and streams (torch's current stream).
+If the library has not been built the first call raises GempeLibraryMissing: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgempe.so")
+
+GEMPE_OK = 0
+GEMPE_ERR_ARG = -1
+GEMPE_ERR_GRAPH = -2
+GEMPE_ERR_NOMEM = -3
+GEMPE_ERR_HIP = -4
+GEMPE_ERR_NUMERIC = -5
+GEMPE_ERR_UNSUPPORTED = -6
+GEMPE_ERR_TIMEOUT = -7
+
+GEMPE_FP32 = 0
+GEMPE_BF16_GRAM = 1
+
+# Every symbol include/gempe.h declares (checked by the tests).
+ABI_SYMBOLS = (
+    "gempe_params_default",
+    "gempe_graph_create",
+    "gempe_graph_destroy",
+    "gempe_graph_num_vertices",
+    "gempe_graph_num_edges",
+    "gempe_has_edge",
+    "gempe_workspace_bytes",
+    "gempe_loss_grad",
+    "gempe_step",
+    "gempe_embed",
+    "gempe_status_string",
+    "gempe_last_error",
+)
+
+
+class GempeLibraryMissing(RuntimeError):
+    pass
+
+
+class GempeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gempe status {status}: {message}")
+        self.status = status
+
+
+class gempe_params(ctypes.Structure):
+    _fields_ = [
+        ("mu", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("near_k", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+        ("reserved1", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads libgempe.so (once) and declares the ABI's signatures."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise GempeLibraryMissing(
+            f"{p} is not built; run `python -m paper_2011_03479_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    st = ctypes.c_int
+    P = ctypes.POINTER(gempe_params)
+    lib.gempe_params_default.argtypes = [P]
+    lib.gempe_params_default.restype = None
+    lib.gempe_graph_create.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.gempe_graph_create.restype = st
+    lib.gempe_graph_destroy.argtypes = [vp]
+    lib.gempe_graph_destroy.restype = st
+    lib.gempe_graph_num_vertices.argtypes = [vp]
+    lib.gempe_graph_num_vertices.restype = ctypes.c_int32
+    lib.gempe_graph_num_edges.argtypes = [vp]
+    lib.gempe_graph_num_edges.restype = ctypes.c_int64
+    lib.gempe_has_edge.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+    lib.gempe_has_edge.restype = st
+    lib.gempe_workspace_bytes.argtypes = [vp, ctypes.c_int32, P]
+    lib.gempe_workspace_bytes.restype = ctypes.c_size_t
+    lib.gempe_loss_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_loss_grad.restype = st
+    lib.gempe_step.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_float, vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_step.restype = st
+    lib.gempe_embed.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_float, vp, vp,
+                                ctypes.c_size_t, P, vp]
+    lib.gempe_embed.restype = st
+    lib.gempe_status_string.argtypes = [st]
+    lib.gempe_status_string.restype = ctypes.c_char_p
+    lib.gempe_last_error.argtypes = []
+    lib.gempe_last_error.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != GEMPE_OK:
+        lib = load()
+        raise GempeError(status, lib.gempe_last_error().decode())
+
+
+def params_default(**over) -> gempe_params:
+    p = gempe_params()
+    load().gempe_params_default(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def status_string(s: int) -> str:
+    return load().gempe_status_string(int(s)).decode()
+
+
+def last_error() -> str:
+    return load().gempe_last_error().decode()
+
+
+# ------------------------------------------------------------------------------------
+# torch marshalling
+# ------------------------------------------------------------------------------------
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Graph:
+    """Owns a gempe_graph handle built from CSR arrays (numpy or CUDA tensors)."""
+
+    def __init__(self, n: int, row_ptr, col_idx, device="cuda", stream=None):
+        torch = _torch()
+        lib = load()
+        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64) if not torch.is_tensor(row_ptr) else row_ptr,
+                             dtype=torch.int64, device=device).contiguous()
+        ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32) if not torch.is_tensor(col_idx) else col_idx,
+                             dtype=torch.int32, device=device).contiguous()
+        if ci.numel() == 0:
+            ci = torch.zeros(1, dtype=torch.int32, device=device)
+            nnz = 0
+        else:
+            nnz = int(ci.numel())
+        h = ctypes.c_void_p()
+        _check(lib.gempe_graph_create(int(n), nnz, _ptr(rp), _ptr(ci), _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n = int(n)
+        self.nnz = nnz
+
+    @property
+    def m(self) -> int:
+        return int(load().gempe_graph_num_edges(self.handle))
+
+    def num_vertices(self) -> int:
+        return int(load().gempe_graph_num_vertices(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(load().gempe_graph_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def graph_create(n, row_ptr, col_idx, stream=None) -> Graph:
+    return Graph(n, row_ptr, col_idx, stream=stream)
+
+
+def has_edge(g: Graph, qi, qj, stream=None):
+    torch = _torch()
+    qi = torch.as_tensor(qi, dtype=torch.int32, device="cuda").contiguous()
+    qj = torch.as_tensor(qj, dtype=torch.int32, device="cuda").contiguous()
+    out = torch.empty(qi.numel(), dtype=torch.uint8, device="cuda")
+    _check(load().gempe_has_edge(g.handle, int(qi.numel()), _ptr(qi), _ptr(qj), _ptr(out), _stream(stream)))
+    return out
+
+
+def workspace_bytes(g: Graph, d: int, params: gempe_params | None = None) -> int:
+    p = params or params_default()
+    nbytes = int(load().gempe_workspace_bytes(g.handle, int(d), ctypes.byref(p)))
+    if nbytes == 0:
+        raise GempeError(GEMPE_ERR_ARG, last_error())
+    return nbytes
+
+
+def workspace(g: Graph, d: int, params: gempe_params | None = None):
+    """A torch uint8 CUDA tensor of workspace_bytes (torch allocations are 256-B aligned)."""
+    torch = _torch()
+    return torch.empty(workspace_bytes(g, d, params), dtype=torch.uint8, device="cuda")
+
+
+@dataclass
+class LossGrad:
+    loss: "object"        # float64[1] tensor
+    grad: "object"        # float32[n, d] tensor or None
+    edge_hits: "object"   # int64[1] tensor or None
+    row_loss: "object"    # float32[n] tensor or None
+
+
+def loss_grad(g: Graph, X, ws=None, params=None, want_grad=True, want_hits=True, want_row_loss=False,
+              stream=None, out: LossGrad | None = None) -> LossGrad:
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    if out is None:
+        out = LossGrad(
+            loss=torch.empty(1, dtype=torch.float64, device="cuda"),
+            grad=torch.empty((n, d), dtype=torch.float32, device="cuda") if want_grad else None,
+            edge_hits=torch.empty(1, dtype=torch.int64, device="cuda") if want_hits else None,
+            row_loss=torch.empty(n, dtype=torch.float32, device="cuda") if want_row_loss else None,
+        )
+    _check(load().gempe_loss_grad(g.handle, int(d), _ptr(X), _ptr(out.grad), _ptr(out.loss), _ptr(out.edge_hits),
+                                  _ptr(out.row_loss), _ptr(ws), int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return out
+
+
+def step(g: Graph, X, eta: float, ws=None, params=None, loss_before=None, stream=None):
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    _check(load().gempe_step(g.handle, int(d), _ptr(X), float(eta), _ptr(loss_before), _ptr(ws), int(ws.numel()),
+                             ctypes.byref(p), _stream(stream)))
+    return X
+
+
+def embed(g: Graph, X, iters: int, eta: float, ws=None, params=None, loss_hist=None, stream=None):
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    _check(load().gempe_embed(g.handle, int(d), _ptr(X), int(iters), float(eta), _ptr(loss_hist), _ptr(ws),
+                              int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return X

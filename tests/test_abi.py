@@ -1,0 +1,64 @@
+"""The C-ABI library loads on the CPU host and exports every symbol include/gempe.h declares.
+
+No compute call is made here (there is no GPU); only host-side argument checks that return
+before anything touches the device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2011_03479_amd import gempe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "gempe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(gempe_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gempe.LIB_PATH):
+        pytest.fail("libgempe.so is not built (run python -m paper_2011_03479_amd.build)")
+    return gempe.load()
+
+
+def test_header_matches_binding_list():
+    assert header_functions() == sorted(gempe.ABI_SYMBOLS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_params_default_and_status_strings(lib):
+    p = gempe.params_default()
+    assert (p.mu, p.sigma, p.precision, p.near_k, p.flags) == (1.5, 1.0, gempe.GEMPE_FP32, 9.0, 0)
+    assert ctypes.sizeof(gempe.gempe_params) == 40
+    for s in range(0, -8, -1):
+        assert gempe.status_string(s) not in ("", "unknown status")
+    assert gempe.status_string(42) == "unknown status"
+
+
+def test_host_side_argument_checks(lib):
+    out = ctypes.c_void_p()
+    assert lib.gempe_graph_create(10, 0, None, None, None, None) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_graph_create(0, 0, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_graph_create(10, 3, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
+    assert lib.gempe_graph_create(3, 8, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
+    assert "nnz" in gempe.last_error()
+    p = gempe.params_default()
+    assert lib.gempe_workspace_bytes(None, 2, ctypes.byref(p)) == 0
+    assert lib.gempe_loss_grad(None, 2, None, None, None, None, None, None, 0, ctypes.byref(p), None) == \
+        gempe.GEMPE_ERR_ARG
+    assert lib.gempe_embed(None, 2, None, 1, ctypes.c_float(0.1), None, None, 0, ctypes.byref(p), None) == \
+        gempe.GEMPE_ERR_ARG
+    assert lib.gempe_graph_num_edges(None) == -1 and lib.gempe_graph_num_vertices(None) == -1
+    assert lib.gempe_graph_destroy(None) == gempe.GEMPE_ERR_ARG
