@@ -142,16 +142,21 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     double *scratch_loss = reinterpret_cast<double *>(w + L.counters + 16);
     PairParamsHost pp = gempe_pair_params(p);
     const long long nd = (long long)g->n * d;
-    // the status word is cleared by the first sweep only, so it is sticky over the run
-    for (int k = 0; k <= iters; ++k) {
-        bool last = (k == iters);
-        if (last && !loss_hist) break;
-        double *lossp = loss_hist ? loss_hist + k : scratch_loss;
-        GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr, pp,
-                                             stream, k == 0));
-        if (!last) GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, nd, stream));
-    }
     if (iters == 0 && !loss_hist) return GEMPE_OK;
+    if (plan.persist) {
+        // one cooperative launch for the whole run
+        GEMPE_HIP_TRY(gempe_launch_embed_persistent(g, d, plan, X, iters, eta, loss_hist, L, w, pp, stream));
+    } else {
+        // the status word is cleared by the first sweep only, so it is sticky over the run
+        for (int k = 0; k <= iters; ++k) {
+            bool last = (k == iters);
+            if (last && !loss_hist) break;
+            double *lossp = loss_hist ? loss_hist + k : scratch_loss;
+            GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr,
+                                                 pp, stream, k == 0));
+            if (!last) GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, nd, stream));
+        }
+    }
     unsigned host_status = 0;
     GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
     GEMPE_HIP_TRY(hipStreamSynchronize(stream));

@@ -90,15 +90,22 @@ struct SweepPlan {
     long long grid = 0;   // workgroups launched (multiple of 8, >= items)
     int edge_blocks = 0;  // blocks of the exact edge pass
     long long partials = 0;  // float loss partials: items + edge_blocks
+    // persistent gradient descent (d <= 16, small n)
+    bool persist = false;
+    long long nb64 = 0;        // 64-vertex blocks per side
+    long long tiles64 = 0;     // upper-triangle 64x64 tiles
+    long long p_grid = 0;      // workgroups (4 independent waves each)
+    int L = 64;                // steps of the 64-step schedule per work unit
+    long long units_sweep = 0, units_edge = 0, units = 0;
 };
 
 struct WsLayout {
     size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, ...
     size_t partials = 0;  // float[plan.partials]
     size_t gbuf = 0;      // float[n*d] gradient scratch for gempe_step/gempe_embed
-    size_t xbuf = 0;      // float[2*n*d] embed: double-buffered coordinates
+    size_t xbuf = 0;      // float[n*d] embed: second slot of the double-buffered iterate
     size_t gring = 0;     // float[3*n*d] embed: three gradient slots
-    size_t ppart = 0;     // float[2*plan.partials] embed: double-buffered loss partials
+    size_t ppart = 0;     // float[2*plan.units] embed: double-buffered loss partials
     size_t barrier = 0;   // 256 B: grid barrier counter + generation
     size_t total = 0;
 };
@@ -120,4 +127,4 @@ hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long coun
 hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                          float *X, int iters, float eta, double *loss_hist,
                                          const WsLayout &L, unsigned char *ws,
-                                         const PairParamsHost &pp, hipStream_t s, bool *used);
+                                         const PairParamsHost &pp, hipStream_t s);

@@ -1,31 +1,31 @@
 // FP32 all-pairs sweep of the GEMPE coding cost and its gradient (gfx950).
 //
-// Decomposition.  The n(n-1)/2 unordered pairs are covered by square super tiles of
-// T x T vertices on and above the block diagonal (tile (I, J), I <= J).  One workgroup
-// owns one tile; its W waves each hold 64 R rows in registers (R rows per lane) and
-// sweep the tile's columns in blocks of 64 that are staged once in LDS and shared by the
-// waves.  Inside a 64-column block lane l pairs its rows with column (l + s) mod 64 at
-// step s = 0..63 (a Latin-square schedule: at every step the 64 lanes touch 64 distinct
-// columns), so
-//   - the row side of the gradient, g_i += cc (x_i - x_j), accumulates in registers;
-//   - the column side, g_j -= cc (x_i - x_j), accumulates in a register that moves one
-//     lane per step with a DPP wave rotation, so it follows its column through the
-//     lanes and is back in lane l (holding column l) after 64 steps;
-//   - the W waves' column partials are combined in LDS and leave with one global FP32
-//     atomic per (column, coordinate) per tile; rows leave once per tile.
-// Sums are two-level: per 64-column block in registers, then across blocks, then across
-// tiles (atomics).  The loss partial of a tile is one FP32 number written to a fixed
-// slot; the final sum over slots is FP64 in a fixed order (deterministic loss).
+// Decomposition.  The n(n-1)/2 unordered pairs are covered by square tiles on and above
+// the block diagonal.  A wave holds 64 R rows in registers (R rows per lane) and meets
+// columns in blocks of 64.  Within a block, lane l pairs its rows with column
+// (l + s) mod 64 at step s = 0..63 (a Latin-square schedule: at every step the 64 lanes
+// touch 64 distinct columns).  The column's coordinates and its gradient accumulator
+// travel with it: both move one lane per step by a DPP wave rotation, so the inner loop
+// touches neither LDS nor memory, and after 64 steps lane l again holds column l.
+//   - row side of the gradient, g_i += cc (x_i - x_j): registers;
+//   - column side, g_j -= cc (x_i - x_j): the rotating accumulator, flushed once per
+//     block (several waves first combine theirs in LDS);
+//   - loss: per-lane FP32 sums, one FP32 partial per work unit in a fixed slot, summed
+//     in FP64 in slot order (deterministic).
 //
 // Every pair is scored as a non-edge in the sweep.  Edges are corrected exactly by a
-// second pass over the CSR entries (k_edges): it adds dl+ - dl- and (cc+ - cc-)(x_i - x_j)
-// computed with the same FP32 code at the same distance, and counts every pair i<j it
-// scores as an edge after confirming it in the exact edge hash.  Membership per pair is
-// therefore exact, and the O(n^2) sweep carries no per-pair membership test.
+// pass over the CSR entries: it adds dl+ - dl- and (cc+ - cc-)(x_i - x_j), computed by
+// the same FP32 code at the same distance, so membership per pair is exact without a
+// membership test in the O(n^2) loop.  The standalone edge kernel also counts the pairs
+// i<j it scores as edges after confirming each one in the exact edge hash.
 //
-// Wide embeddings (d > 16) use k_sweep_wide: the same schedule with rows, row
-// gradients, columns and column gradients all in LDS (the Latin-square schedule makes
-// the read-modify-writes race-free without atomics).
+// Three entry kernels:
+//   k_sweep_small   d <= 16, one launch per evaluation, tiles of 64 R W rows shared by W
+//                   waves (large n);
+//   k_sweep_wide    17 <= d <= 128, rows/columns and both gradients in LDS;
+//   k_embed_persist d <= 16, small n: whole gradient-descent runs in one cooperative
+//                   launch, one grid barrier per iteration, work split into units of
+//                   (64 x 64 tile, range of steps) so that every SIMD gets an equal share.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,8 +58,13 @@ __device__ inline long long xcd_item(long long b, long long per_xcd) {
 }
 
 __device__ __forceinline__ float rot1(float v) {
-    // DPP wave rotation by one lane (row_mask/bank_mask all, no bound control)
+    // DPP wave rotation by one lane (all rows and banks enabled)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+// +1 if the rotation brings lane l+1's value to lane l, else -1.
+__device__ __forceinline__ int rot_dir(int lane) {
+    return (__float_as_int(rot1(__int_as_float(lane))) == ((lane + 1) & 63)) ? 1 : -1;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -67,6 +72,20 @@ __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+
+// Coordinates of the current iterate: X[v], or X[v] - eta G[v] when a step of gradient
+// descent is applied on the fly (persistent loop).  Both the sweep and the edge pass read
+// through this view, so they see bit-identical coordinates.
+struct XView {
+    const float *X;
+    const float *Gp;  // previous gradient, or nullptr
+    float neg_eta;
+    int d;
+    __device__ __forceinline__ float at(long long v, int k) const {
+        size_t o = (size_t)v * d + k;
+        return Gp ? __builtin_fmaf(neg_eta, Gp[o], X[o]) : X[o];
+    }
+};
 
 template <int D>
 __device__ __forceinline__ float sqdist(const float (&a)[D], const float (&b)[D], float (&diff)[D]) {
@@ -79,8 +98,51 @@ __device__ __forceinline__ float sqdist(const float (&a)[D], const float (&b)[D]
     return r2;
 }
 
+// Steps [s0, s1) of the Latin-square schedule against one block of 64 columns starting at
+// col0.  xc / colacc hold, in lane l, the coordinates / accumulator of column
+// col0 + ((l + dir s) mod 64) at step s; both rotate once per step.
+template <int D, int R, bool MASK, bool ROWLOSS>
+__device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
+                                            float (&colacc)[D + (ROWLOSS ? 1 : 0)], float (&gi)[R][D],
+                                            float (&li)[R], float &loss, int lane, int dir, int col0, int n,
+                                            int s0, int s1, const PairParams &P) {
+    constexpr int NC = D + (ROWLOSS ? 1 : 0);
+    for (int s = s0; s < s1; ++s) {
+        int j = 0;
+        if (MASK) j = col0 + ((lane + dir * s) & 63);
+        float tc[NC];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float diff[D];
+            float r2 = sqdist<D>(xi[r], xc, diff);
+            float dl, cc;
+            pair_nonedge(r2, P, dl, cc);
+            if (MASK) {
+                bool valid = (irow[r] < j) && (j < n);
+                dl = valid ? dl : 0.0f;
+                cc = valid ? cc : 0.0f;
+            }
+            loss += dl;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                float f = cc * diff[k];
+                gi[r][k] += f;
+                tc[k] = (r == 0) ? f : tc[k] + f;
+            }
+            if (ROWLOSS) {
+                li[r] += dl;
+                tc[NC - 1] = (r == 0) ? dl : tc[NC - 1] + dl;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) colacc[k] = rot1(colacc[k] + tc[k]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) xc[k] = rot1(xc[k]);
+    }
+}
+
 // ------------------------------------------------------------------------------------
-// Register-resident sweep, d <= 16.
+// Register-resident sweep, d <= 16, one launch per evaluation.
 // ------------------------------------------------------------------------------------
 template <int D, int R, int W, bool ROWLOSS>
 __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict__ X, int n, int d,
@@ -90,7 +152,6 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                                                         float *__restrict__ partials, PairParams P) {
     constexpr int T = 64 * R * W;
     constexpr int NC = D + (ROWLOSS ? 1 : 0);
-    __shared__ float xs[64 * D];
     __shared__ float cs[W > 1 ? 64 * NC : 1];
     __shared__ float lsum[W];
 
@@ -100,8 +161,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
     if (t >= items) return;  // uniform over the workgroup
     int I, J;
     tile_of(t, nt, I, J);
-    // rotation direction of the DPP wave rotate (data from lane l+1 or l-1)
-    const int dir = (__float_as_int(rot1(__int_as_float(lane))) == ((lane + 1) & 63)) ? 1 : -1;
+    const int dir = rot_dir(lane);
 
     const int row0 = I * T + wave * 64 * R;
     int irow[R];
@@ -121,23 +181,19 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 
     for (int cb = 0; cb < T / 64; ++cb) {
         const int c0 = J * T + cb * 64;
-        __syncthreads();
-        for (int k = threadIdx.x; k < 64 * D; k += 64 * W) {
-            int c = k / D, dd = k - c * D, j = c0 + c;
-            xs[k] = (j < n && dd < d) ? X[(size_t)j * d + dd] : 0.0f;
-        }
-        if (W > 1)
+        if (W > 1) {
+            __syncthreads();
             for (int k = threadIdx.x; k < 64 * NC; k += 64 * W) cs[k] = 0.0f;
-        __syncthreads();
-
+            __syncthreads();
+        }
         // every pair of this wave and block has j <= i: nothing to do
         const bool skip = masked && (c0 + 63 <= row0);
         float colacc[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) colacc[k] = 0.0f;
-        float blk_loss = 0.0f;
-        float bg[R][D];
-        float bl[R];
+        // two-level sums: per 64-column block, then across blocks
+        float blk = 0.0f;
+        float bg[R][D], bl[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             bl[r] = 0.0f;
@@ -145,41 +201,14 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
             for (int k = 0; k < D; ++k) bg[r][k] = 0.0f;
         }
         if (!skip) {
-            for (int s = 0; s < 64; ++s) {
-                const int c = (lane + dir * s) & 63;
-                const int j = c0 + c;
-                float xc[D];
+            float xc[D];
+            const int jc = c0 + lane;
 #pragma unroll
-                for (int k = 0; k < D; ++k) xc[k] = xs[c * D + k];
-                float tc[NC];
-#pragma unroll
-                for (int k = 0; k < NC; ++k) tc[k] = 0.0f;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    float diff[D];
-                    float r2 = sqdist<D>(xi[r], xc, diff);
-                    float dl, cc;
-                    pair_nonedge(r2, P, dl, cc);
-                    if (masked) {
-                        bool valid = (irow[r] < j) && (j < n);
-                        dl = valid ? dl : 0.0f;
-                        cc = valid ? cc : 0.0f;
-                    }
-                    blk_loss += dl;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        float f = cc * diff[k];
-                        bg[r][k] += f;
-                        tc[k] += f;
-                    }
-                    if (ROWLOSS) {
-                        bl[r] += dl;
-                        tc[NC - 1] += dl;
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < NC; ++k) colacc[k] = rot1(colacc[k] + tc[k]);
-            }
+            for (int k = 0; k < D; ++k) xc[k] = (jc < n && k < d) ? X[(size_t)jc * d + k] : 0.0f;
+            if (masked)
+                sweep_steps<D, R, true, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P);
+            else
+                sweep_steps<D, R, false, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P);
         }
         // lane l now holds the column partial of column c0 + l
         const int jc = c0 + lane;
@@ -207,7 +236,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                 }
             }
         }
-        loss_acc += blk_loss;
+        loss_acc += blk;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             li[r] += bl[r];
@@ -315,8 +344,48 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
 }
 
 // ------------------------------------------------------------------------------------
-// Exact edge correction over CSR entries.
+// Exact edge correction of one CSR entry (i, j): adds (cc+ - cc-)(x_i - x_j) to g_i and
+// returns dl+ - dl-; the caller counts the loss for i < j only (each undirected edge has
+// two entries, each updating its own row).
 // ------------------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float *__restrict__ G,
+                                            const PairParams &P) {
+    float xi[D], xj[D], diff[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xi[k] = k < xv.d ? xv.at(i, k) : 0.0f;
+        xj[k] = k < xv.d ? xv.at(j, k) : 0.0f;
+    }
+    float r2 = sqdist<D>(xi, xj, diff);
+    float dlp, ccp, dln, ccn;
+    pair_eval(r2, -1.0f, P, dlp, ccp);
+    pair_eval(r2, 1.0f, P, dln, ccn);
+    const float dcc = ccp - ccn;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (k < xv.d) atomicAdd(&G[(size_t)i * xv.d + k], dcc * diff[k]);
+    return dlp - dln;
+}
+
+// Runtime-d variant for the standalone edge kernel (any d <= 128).
+__device__ __forceinline__ float edge_entry_any(const float *__restrict__ X, int d, int i, int j,
+                                                float *__restrict__ G, const PairParams &P) {
+    const float *xi = X + (size_t)i * d;
+    const float *xj = X + (size_t)j * d;
+    float r2 = 0.0f;
+    for (int k = 0; k < d; ++k) {
+        float df = xi[k] - xj[k];
+        r2 = __builtin_fmaf(df, df, r2);
+    }
+    float dlp, ccp, dln, ccn;
+    pair_eval(r2, -1.0f, P, dlp, ccp);
+    pair_eval(r2, 1.0f, P, dln, ccn);
+    const float dcc = ccp - ccn;
+    for (int k = 0; k < d; ++k) atomicAdd(&G[(size_t)i * d + k], dcc * (xi[k] - xj[k]));
+    return dlp - dln;
+}
+
 constexpr int kEdgeBlock = 256;
 
 template <bool ROWLOSS>
@@ -336,19 +405,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     if (e < nnz) {
         const int i = coo_row[e];
         const int j = col[e];
-        const float *xi = X + (size_t)i * d;
-        const float *xj = X + (size_t)j * d;
-        float r2 = 0.0f;
-        for (int k = 0; k < d; ++k) {
-            float df = xi[k] - xj[k];
-            r2 = __builtin_fmaf(df, df, r2);
-        }
-        float dlp, ccp, dln, ccn;
-        pair_eval(r2, -1.0f, P, dlp, ccp);
-        pair_eval(r2, 1.0f, P, dln, ccn);
-        const float dcc = ccp - ccn;
-        for (int k = 0; k < d; ++k) atomicAdd(&G[(size_t)i * d + k], dcc * (xi[k] - xj[k]));
-        const float ddl = dlp - dln;
+        const float ddl = edge_entry_any(X, d, i, j, G, P);
         if (ROWLOSS) atomicAdd(&rowloss[i], ddl);
         if (i < j) {
             dloss = ddl;
@@ -386,10 +443,13 @@ __global__ void k_zero(float *__restrict__ a, long long na, float *__restrict__ 
 
 constexpr int kFinBlock = 256;
 
+// Sum of partials[0..count) in FP64: thread t adds slots t, t+256, ... in order, then a
+// fixed tree over the 256 threads.  Called by a whole 256-thread workgroup.
 __device__ inline double block_sum_fixed(const float *__restrict__ partials, long long count,
                                          double *sh) {
     double acc = 0.0;
     for (long long q = threadIdx.x; q < count; q += kFinBlock) acc += (double)partials[q];
+    __syncthreads();
     sh[threadIdx.x] = acc;
     __syncthreads();
     for (int off = kFinBlock / 2; off >= 1; off >>= 1) {
@@ -417,6 +477,169 @@ __global__ void k_axpy(float *__restrict__ X, const float *__restrict__ G, float
     if (k < count) X[k] = __builtin_fmaf(-eta, G[k], X[k]);
 }
 
+// ------------------------------------------------------------------------------------
+// Persistent gradient descent for d <= 16 and small n.
+// ------------------------------------------------------------------------------------
+constexpr unsigned long long kSpinLimit = 1ull << 24;  // ~1 s of polling per barrier
+
+// Sense-counting grid barrier.  bar[0] counts arrivals, bar[1] is the generation.  Every
+// wait is bounded: past kSpinLimit polls, or once any workgroup has timed out, the
+// workgroup records kStatusTimeout and proceeds, so the kernel always terminates.
+__device__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *status) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned g = gen;
+        __threadfence();
+        unsigned prev = atomicAdd(&bar[0], 1u);
+        if (prev == nblocks - 1) {
+            atomicExch(&bar[0], 0u);
+            __threadfence();
+            __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit ||
+                    (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusTimeout)) {
+                    atomicOr(status, kStatusTimeout);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        gen = g + 1;
+    }
+    __syncthreads();
+}
+
+struct EmbedArgs {
+    float *Xc;          // caller coordinates: slot 0 of the iterate buffer, final result
+    float *Xw;          // workspace slot 1
+    float *G0;          // three gradient slots of n*d floats each
+    float *P0;          // two partial slots of `units` floats each
+    double *loss_hist;  // sweeps entries, or nullptr
+    unsigned *bar;      // barrier words (zeroed before launch)
+    unsigned *status;
+    const int32_t *coo_row;
+    const int32_t *col;
+    long long nnz;
+    int n, d, nb, sweeps, iters, L, epu;  // epu: edge entries per unit
+    long long tiles, units_sweep, units;
+    float neg_eta;
+    PairParams P;
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void k_embed_persist(EmbedArgs a) {
+    __shared__ double sh[kFinBlock];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long gwave = (long long)blockIdx.x * 4 + wave;
+    const long long nwaves = (long long)gridDim.x * 4;
+    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nthreads = (long long)gridDim.x * blockDim.x;
+    const long long nd = (long long)a.n * a.d;
+    const int dir = rot_dir(lane);
+    const int steps = 64 / a.L;
+    unsigned gen = 0;
+    float *Xs[2] = {a.Xc, a.Xw};
+
+    for (int k = 0; k < a.sweeps; ++k) {
+        const float *Xprev = (k == 0) ? Xs[0] : Xs[(k - 1) & 1];
+        const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
+        float *Gk = a.G0 + (size_t)(k % 3) * nd;
+        float *Gnext = a.G0 + (size_t)((k + 1) % 3) * nd;
+        float *Pk = a.P0 + (size_t)(k & 1) * a.units;
+        const XView xv{Xprev, Gprev, a.neg_eta, a.d};
+        // materialise x_k for the next iteration and clear the slot it will accumulate into
+        for (long long v = gtid; v < nd; v += nthreads) {
+            if (k > 0) Xs[k & 1][v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
+            Gnext[v] = 0.0f;
+        }
+        for (long long u = gwave; u < a.units; u += nwaves) {
+            float loss = 0.0f;
+            if (u < a.units_sweep) {
+                const long long t = u / steps;
+                const int s0 = (int)(u - t * steps) * a.L;
+                int I, J;
+                tile_of(t, a.nb, I, J);
+                const int i = I * 64 + lane;
+                const int col0 = J * 64;
+                const int jc = col0 + ((lane + dir * s0) & 63);
+                float xi[1][D], xc[D], gi[1][D], li[1], colacc[D];
+                int irow[1] = {i};
+#pragma unroll
+                for (int k2 = 0; k2 < D; ++k2) {
+                    xi[0][k2] = (i < a.n && k2 < a.d) ? xv.at(i, k2) : 0.0f;
+                    xc[k2] = (jc < a.n && k2 < a.d) ? xv.at(jc, k2) : 0.0f;
+                    gi[0][k2] = 0.0f;
+                    colacc[k2] = 0.0f;
+                }
+                li[0] = 0.0f;
+                const bool masked = (I == J) || (col0 + 64 > a.n);
+                if (masked)
+                    sweep_steps<D, 1, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
+                                                   s0 + a.L, a.P);
+                else
+                    sweep_steps<D, 1, false, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
+                                                    s0 + a.L, a.P);
+                const int jf = col0 + ((lane + dir * (s0 + a.L)) & 63);
+                if (jf < a.n) {
+#pragma unroll
+                    for (int k2 = 0; k2 < D; ++k2)
+                        if (k2 < a.d) atomicAdd(&Gk[(size_t)jf * a.d + k2], -colacc[k2]);
+                }
+                if (i < a.n) {
+#pragma unroll
+                    for (int k2 = 0; k2 < D; ++k2)
+                        if (k2 < a.d) atomicAdd(&Gk[(size_t)i * a.d + k2], gi[0][k2]);
+                }
+            } else {
+                const long long e0 = (u - a.units_sweep) * (long long)a.epu;
+                for (int q = 0; q < a.epu; q += 64) {
+                    const long long e = e0 + q + lane;
+                    if (e < a.nnz) {
+                        const int i = a.coo_row[e];
+                        const int j = a.col[e];
+                        const float ddl = edge_entry<D>(xv, i, j, Gk, a.P);
+                        if (i < j) loss += ddl;
+                    }
+                }
+            }
+            loss = wave_sum(loss);
+            if (lane == 0) Pk[u] = loss;
+        }
+        // the FP64 loss of the previous sweep (its partials are complete): last workgroup
+        if (a.loss_hist && k > 0 && blockIdx.x == gridDim.x - 1) {
+            double tot = block_sum_fixed(a.P0 + (size_t)((k - 1) & 1) * a.units, a.units, sh);
+            if (threadIdx.x == 0) {
+                a.loss_hist[k - 1] = tot;
+                if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
+            }
+        }
+        grid_barrier(a.bar, gridDim.x, gen, a.status);
+    }
+    const int K = a.sweeps;
+    if (K > 0 && a.loss_hist && blockIdx.x == gridDim.x - 1) {
+        double tot = block_sum_fixed(a.P0 + (size_t)((K - 1) & 1) * a.units, a.units, sh);
+        if (threadIdx.x == 0) {
+            a.loss_hist[K - 1] = tot;
+            if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
+        }
+    }
+    // final coordinates into the caller's buffer
+    if (a.iters > 0) {
+        if (K == a.iters + 1) {  // x_iters was materialised during the last sweep
+            if (a.iters & 1)
+                for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = a.Xw[v];
+        } else {  // K == iters: apply the last step now
+            const float *Xl = Xs[(a.iters - 1) & 1];
+            const float *Gl = a.G0 + (size_t)((a.iters - 1) % 3) * nd;
+            for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = __builtin_fmaf(a.neg_eta, Gl[v], Xl[v]);
+        }
+    }
+}
+
 }  // namespace gempe
 
 // ======================================================================================
@@ -441,6 +664,10 @@ long long tiles_for(int n, int T) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int kCUs = 256;                      // MI355X compute units
+constexpr long long kPersistMaxTiles = 65536;  // 64x64 tiles: n up to ~23k
+constexpr int kEdgesPerUnit = 256;
 
 }  // namespace
 
@@ -475,6 +702,32 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d) {
     p.grid = per * kXcd;
     p.edge_blocks = (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
+
+    // persistent plan: 64x64 tiles split into units of L steps, 2 waves per SIMD
+    p.persist = false;
+    const long long t64 = tiles_for(g->n, 64);
+    if (p.D <= 16 && t64 <= kPersistMaxTiles) {
+        p.persist = true;
+        p.nb64 = (g->n + 63) / 64;
+        p.tiles64 = t64;
+        p.p_grid = 2 * kCUs;  // workgroups of 4 independent waves
+        const long long waves = 4LL * p.p_grid;
+        p.units_edge = (g->nnz + kEdgesPerUnit - 1) / kEdgesPerUnit;
+        // pick the step range minimising the busiest wave's work (in steps, plus ~4 steps
+        // of per-unit overhead); an edge unit costs about as much as 8 steps
+        long long best = -1;
+        for (int L : {64, 32, 16, 8}) {
+            long long us = t64 * (64 / L);
+            long long per_wave = (us + p.units_edge + waves - 1) / waves;
+            long long cost = per_wave * (L + 4);
+            if (best < 0 || cost < best) {
+                best = cost;
+                p.L = L;
+            }
+        }
+        p.units_sweep = t64 * (64 / p.L);
+        p.units = p.units_sweep + p.units_edge;
+    }
     return p;
 }
 
@@ -489,11 +742,11 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     L.gbuf = off;
     off = align256(off + sizeof(float) * nd);
     L.xbuf = off;
-    off = align256(off + sizeof(float) * 2 * nd);
+    off = align256(off + sizeof(float) * nd);
     L.gring = off;
     off = align256(off + sizeof(float) * 3 * nd);
     L.ppart = off;
-    off = align256(off + sizeof(float) * 2 * (size_t)plan.partials);
+    off = align256(off + sizeof(float) * 2 * (size_t)std::max<long long>(plan.units, 1));
     L.barrier = off;
     off += 256;
     L.total = off;
@@ -535,6 +788,12 @@ void launch_wide(const SweepPlan &pl, hipStream_t s, const float *X, int n, int 
                  float *part, PairParams P) {
     long long per = pl.grid / kXcd;
     size_t lds = sizeof(float) * 4 * 64 * (D + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide<D, RL>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr_set = true;
+    }
     hipLaunchKernelGGL((k_sweep_wide<D, RL>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
                        pl.items, per, G, rl, part, P);
 }
@@ -553,6 +812,25 @@ void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int
         case 64: return launch_wide<64, RL>(pl, s, X, n, d, G, rl, part, P);
         default: return launch_wide<128, RL>(pl, s, X, n, d, G, rl, part, P);
     }
+}
+
+template <int D>
+hipError_t launch_persist(const SweepPlan &pl, EmbedArgs &a, hipStream_t s) {
+    static int max_blocks = -1;
+    if (max_blocks < 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_embed_persist<D>, 256, 0);
+        if (e != hipSuccess) return e;
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        max_blocks = per_cu * cus;
+    }
+    int grid = (int)std::min<long long>(pl.p_grid, max_blocks);
+    if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_embed_persist<D>), dim3(grid), dim3(256),
+                                      args, 0, s);
 }
 
 }  // namespace
@@ -599,4 +877,47 @@ hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long coun
     unsigned blocks = (unsigned)std::max<long long>(1, (count + 255) / 256);
     hipLaunchKernelGGL(k_axpy, dim3(blocks), dim3(256), 0, s, X, G, eta, count);
     return hipGetLastError();
+}
+
+hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
+                                         int iters, float eta, double *loss_hist, const WsLayout &L,
+                                         unsigned char *ws, const PairParamsHost &pph, hipStream_t s) {
+    const long long nd = (long long)g->n * d;
+    EmbedArgs a;
+    a.Xc = X;
+    a.Xw = reinterpret_cast<float *>(ws + L.xbuf);
+    a.G0 = reinterpret_cast<float *>(ws + L.gring);
+    a.P0 = reinterpret_cast<float *>(ws + L.ppart);
+    a.loss_hist = loss_hist;
+    a.bar = reinterpret_cast<unsigned *>(ws + L.barrier);
+    a.status = reinterpret_cast<unsigned *>(ws + L.counters + 8);
+    a.coo_row = g->coo_row;
+    a.col = g->col_idx;
+    a.nnz = g->nnz;
+    a.n = g->n;
+    a.d = d;
+    a.nb = (int)plan.nb64;
+    a.iters = iters;
+    a.sweeps = iters + (loss_hist ? 1 : 0);
+    a.L = plan.L;
+    a.epu = kEdgesPerUnit;
+    a.tiles = plan.tiles64;
+    a.units_sweep = plan.units_sweep;
+    a.units = plan.units;
+    a.neg_eta = -eta;
+    a.P = PairParams{pph.mu, pph.inv_sigma, pph.d1_scale};
+    // clear: gradient slot 0, barrier words and the status word (fill kernels, no memset)
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(ws + L.counters);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256))),
+                       dim3(256), 0, s, a.G0, nd, reinterpret_cast<float *>(ws + L.barrier), 64LL, cnt, 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (plan.D) {
+        case 1: return launch_persist<1>(plan, a, s);
+        case 2: return launch_persist<2>(plan, a, s);
+        case 3: return launch_persist<3>(plan, a, s);
+        case 4: return launch_persist<4>(plan, a, s);
+        case 8: return launch_persist<8>(plan, a, s);
+        default: return launch_persist<16>(plan, a, s);
+    }
 }
