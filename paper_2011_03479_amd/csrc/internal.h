@@ -90,13 +90,11 @@ struct SweepPlan {
     long long grid = 0;   // workgroups launched (multiple of 8, >= items)
     int edge_blocks = 0;  // blocks of the exact edge pass
     long long partials = 0;  // float loss partials: items + edge_blocks
-    // persistent gradient descent (d <= 16, small n)
+    // fused-iteration gradient descent (d <= 16, small n): one launch per iteration
     bool persist = false;
     long long nb64 = 0;        // 64-vertex blocks per side
     long long tiles64 = 0;     // upper-triangle 64x64 tiles
-    long long p_grid = 0;      // workgroups (4 independent waves each)
-    int L = 64;                // steps of the 64-step schedule per work unit
-    long long units_sweep = 0, units_edge = 0, units = 0;
+    long long units_sweep = 0, units_edge = 0, units = 0;  // workgroups per iteration
 };
 
 struct WsLayout {
@@ -115,7 +113,7 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 
 // Kernel launchers (sweep.hip).
 struct PairParamsHost {
-    float mu, inv_sigma, d1_scale;  // d1_scale = -1 / (sigma ln 2)
+    float mu_s, inv_sigma, c_neg, c_pos;  // see gempe::PairParams
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 

@@ -9,7 +9,7 @@
 // touches neither LDS nor memory, and after 64 steps lane l again holds column l.
 //   - row side of the gradient, g_i += cc (x_i - x_j): registers;
 //   - column side, g_j -= cc (x_i - x_j): the rotating accumulator, flushed once per
-//     block (several waves first combine theirs in LDS);
+//     block (several waves first combine theirs through private LDS slots);
 //   - loss: per-lane FP32 sums, one FP32 partial per work unit in a fixed slot, summed
 //     in FP64 in slot order (deterministic).
 //
@@ -23,9 +23,10 @@
 //   k_sweep_small   d <= 16, one launch per evaluation, tiles of 64 R W rows shared by W
 //                   waves (large n);
 //   k_sweep_wide    17 <= d <= 128, rows/columns and both gradients in LDS;
-//   k_embed_persist d <= 16, small n: whole gradient-descent runs in one cooperative
-//                   launch, one grid barrier per iteration, work split into units of
-//                   (64 x 64 tile, range of steps) so that every SIMD gets an equal share.
+//   k_iter          d <= 16, small n: one fused launch per gradient-descent iteration
+//                   (sweep, edge pass, previous step, FP64 loss of the previous
+//                   iteration), one workgroup per 64 x 64 tile with its four waves
+//                   splitting the 64 steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,8 +59,14 @@ __device__ inline long long xcd_item(long long b, long long per_xcd) {
 }
 
 __device__ __forceinline__ float rot1(float v) {
-    // DPP wave rotation by one lane (all rows and banks enabled)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, false));
+    // DPP wave rotation by one lane, in place (all rows and banks enabled)
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+// The same rotation written so that the compiler folds it into the consuming add
+// (v_add_f32_dpp): every source lane is valid for a wave rotation.
+__device__ __forceinline__ float rot1_fold(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, true));
 }
 
 // +1 if the rotation brings lane l+1's value to lane l, else -1.
@@ -99,8 +106,11 @@ __device__ __forceinline__ float sqdist(const float (&a)[D], const float (&b)[D]
 }
 
 // Steps [s0, s1) of the Latin-square schedule against one block of 64 columns starting at
-// col0.  xc / colacc hold, in lane l, the coordinates / accumulator of column
-// col0 + ((l + dir s) mod 64) at step s; both rotate once per step.
+// col0.  At step s lane l meets column c_l(s) = col0 + ((l + dir s) mod 64); xc holds that
+// column's coordinates and rotates after each step.  colacc lags one step: before step s
+// it holds the partial of column c_l(s-1) = c_{l-dir}(s), so rotating it by one lane
+// realigns it with c_l(s), and the rotation and this step's addition are one DPP add.
+// After the last step lane l holds the partial of column c_l(s1 - 1).
 template <int D, int R, bool MASK, bool ROWLOSS>
 __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
                                             float (&colacc)[D + (ROWLOSS ? 1 : 0)], float (&gi)[R][D],
@@ -135,7 +145,7 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
             }
         }
 #pragma unroll
-        for (int k = 0; k < NC; ++k) colacc[k] = rot1(colacc[k] + tc[k]);
+        for (int k = 0; k < NC; ++k) colacc[k] = rot1_fold(colacc[k]) + tc[k];
 #pragma unroll
         for (int k = 0; k < D; ++k) xc[k] = rot1(xc[k]);
     }
@@ -152,11 +162,11 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                                                         float *__restrict__ partials, PairParams P) {
     constexpr int T = 64 * R * W;
     constexpr int NC = D + (ROWLOSS ? 1 : 0);
-    __shared__ float cs[W > 1 ? 64 * NC : 1];
+    __shared__ float cs[W > 1 ? W * 64 * NC : 1];  // per-wave column partials
     __shared__ float lsum[W];
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
     int I, J;
@@ -181,11 +191,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 
     for (int cb = 0; cb < T / 64; ++cb) {
         const int c0 = J * T + cb * 64;
-        if (W > 1) {
-            __syncthreads();
-            for (int k = threadIdx.x; k < 64 * NC; k += 64 * W) cs[k] = 0.0f;
-            __syncthreads();
-        }
+        if (W > 1) __syncthreads();  // the previous block's column partials are consumed
         // every pair of this wave and block has j <= i: nothing to do
         const bool skip = masked && (c0 + 63 <= row0);
         float colacc[NC];
@@ -210,8 +216,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
             else
                 sweep_steps<D, R, false, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P);
         }
-        // lane l now holds the column partial of column c0 + l
-        const int jc = c0 + lane;
+        // lane l now holds the partial of column c_l(63)
+        const int jc = c0 + ((lane + 63 * dir) & 63);
         if (W == 1) {
             if (!skip && jc < n) {
 #pragma unroll
@@ -220,18 +226,19 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                 if (ROWLOSS) atomicAdd(&rowloss[jc], colacc[NC - 1]);
             }
         } else {
-            if (!skip) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) atomicAdd(&cs[lane * NC + k], colacc[k]);
-            }
+            for (int k = 0; k < NC; ++k) cs[(wave * 64 + (jc - c0)) * NC + k] = skip ? 0.0f : colacc[k];
             __syncthreads();
             for (int k = threadIdx.x; k < 64 * NC; k += 64 * W) {
                 int c = k / NC, dd = k - c * NC, j = c0 + c;
+                float v = 0.0f;
+#pragma unroll
+                for (int w = 0; w < W; ++w) v += cs[w * 64 * NC + k];
                 if (j < n) {
                     if (dd < D) {
-                        if (dd < d) atomicAdd(&G[(size_t)j * d + dd], -cs[k]);
+                        if (dd < d) atomicAdd(&G[(size_t)j * d + dd], -v);
                     } else if (ROWLOSS) {
-                        atomicAdd(&rowloss[j], cs[k]);
+                        atomicAdd(&rowloss[j], v);
                     }
                 }
             }
@@ -344,13 +351,12 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
 }
 
 // ------------------------------------------------------------------------------------
-// Exact edge correction of one CSR entry (i, j): adds (cc+ - cc-)(x_i - x_j) to g_i and
-// returns dl+ - dl-; the caller counts the loss for i < j only (each undirected edge has
-// two entries, each updating its own row).
+// Exact edge correction of one CSR entry (i, j): the gradient change (cc+ - cc-)(x_i - x_j)
+// of row i, and dl+ - dl- (the caller counts the loss for i < j only: each undirected edge
+// has two entries, each updating its own row).
 // ------------------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float *__restrict__ G,
-                                            const PairParams &P) {
+__device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float (&dg)[D], const PairParams &P) {
     float xi[D], xj[D], diff[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -363,27 +369,23 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
     pair_eval(r2, 1.0f, P, dln, ccn);
     const float dcc = ccp - ccn;
 #pragma unroll
-    for (int k = 0; k < D; ++k)
-        if (k < xv.d) atomicAdd(&G[(size_t)i * xv.d + k], dcc * diff[k]);
+    for (int k = 0; k < D; ++k) dg[k] = dcc * diff[k];
     return dlp - dln;
 }
 
-// Runtime-d variant for the standalone edge kernel (any d <= 128).
-__device__ __forceinline__ float edge_entry_any(const float *__restrict__ X, int d, int i, int j,
-                                                float *__restrict__ G, const PairParams &P) {
-    const float *xi = X + (size_t)i * d;
-    const float *xj = X + (size_t)j * d;
-    float r2 = 0.0f;
-    for (int k = 0; k < d; ++k) {
-        float df = xi[k] - xj[k];
-        r2 = __builtin_fmaf(df, df, r2);
+// Lanes hold values keyed by a row id that is non-decreasing across the active lanes of the
+// wave (CSR order; inactive lanes carry key -1).  Sums each run of equal keys into its first
+// lane (segmented suffix sums, log2(64) shuffle steps) and returns true in those head
+// lanes, so a hub row costs one atomic per wave instead of one per entry.
+__device__ __forceinline__ bool seg_sum_to_head(int key, int lane, float &v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int ko = __shfl_down(key, off, 64);
+        float vo = __shfl_down(v, off, 64);
+        if (lane + off < 64 && ko == key) v += vo;
     }
-    float dlp, ccp, dln, ccn;
-    pair_eval(r2, -1.0f, P, dlp, ccp);
-    pair_eval(r2, 1.0f, P, dln, ccn);
-    const float dcc = ccp - ccn;
-    for (int k = 0; k < d; ++k) atomicAdd(&G[(size_t)i * d + k], dcc * (xi[k] - xj[k]));
-    return dlp - dln;
+    int kp = __shfl_up(key, 1, 64);
+    return key >= 0 && (lane == 0 || kp != key);
 }
 
 constexpr int kEdgeBlock = 256;
@@ -400,19 +402,39 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     __shared__ float wsum[kEdgeBlock / 64];
     __shared__ unsigned whit[kEdgeBlock / 64];
     long long e = (long long)blockIdx.x * kEdgeBlock + threadIdx.x;
-    float dloss = 0.0f;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float dloss = 0.0f, ddl = 0.0f, dcc = 0.0f;
     unsigned hit = 0;
+    int i = -1, j = 0;
     if (e < nnz) {
-        const int i = coo_row[e];
-        const int j = col[e];
-        const float ddl = edge_entry_any(X, d, i, j, G, P);
-        if (ROWLOSS) atomicAdd(&rowloss[i], ddl);
+        i = coo_row[e];
+        j = col[e];
+        const float *xi = X + (size_t)i * d;
+        const float *xj = X + (size_t)j * d;
+        float r2 = 0.0f;
+        for (int k = 0; k < d; ++k) {
+            float df = xi[k] - xj[k];
+            r2 = __builtin_fmaf(df, df, r2);
+        }
+        float dlp, ccp, dln, ccn;
+        pair_eval(r2, -1.0f, P, dlp, ccp);
+        pair_eval(r2, 1.0f, P, dln, ccn);
+        dcc = ccp - ccn;
+        ddl = dlp - dln;
         if (i < j) {
             dloss = ddl;
             hit = gempe_hash_contains(table, cap, gempe_edge_key(i, j)) ? 1u : 0u;
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // row sums of the gradient change (and of the row loss), one atomic per row run
+    for (int k = 0; k < d; ++k) {
+        float v = (i >= 0) ? dcc * (X[(size_t)i * d + k] - X[(size_t)j * d + k]) : 0.0f;
+        if (seg_sum_to_head(i, lane, v)) atomicAdd(&G[(size_t)i * d + k], v);
+    }
+    if (ROWLOSS) {
+        float v = ddl;
+        if (seg_sum_to_head(i, lane, v)) atomicAdd(&rowloss[i], v);
+    }
     float s = wave_sum(dloss);
     unsigned long long b = __ballot(hit != 0);
     if (lane == 0) {
@@ -478,165 +500,165 @@ __global__ void k_axpy(float *__restrict__ X, const float *__restrict__ G, float
 }
 
 // ------------------------------------------------------------------------------------
-// Persistent gradient descent for d <= 16 and small n.
+// Gradient descent for d <= 16 and small n: one fused launch per iteration.
+//
+// Iteration k reads X_{k-1} (iterate slot (k-1)&1) and G_{k-1} (gradient slot (k-1)%3)
+// and applies the previous step on the fly, x_k = X_{k-1} - eta G_{k-1}.  It accumulates
+// G_k into slot k%3, writes x_k into slot k&1 for iteration k+1, clears slot (k+1)%3 (the
+// slot of G_{k-2}, last read by iteration k-1), and writes one FP32 loss partial per work
+// unit into partial slot k&1; workgroup 0 sums the partials of iteration k-1 in FP64.
+// A workgroup takes one 64 x 64 tile, its four waves a quarter of the 64-step schedule
+// each (one per SIMD), and combines their row and column partials in LDS before one
+// global flush; edge workgroups take 4 x 64 CSR entries.  The hardware dispatcher
+// balances the workgroups over the CUs.  The kernel boundary is the only global
+// synchronisation.  (LDS float atomics serialise badly when four waves hit the same
+// lines; the waves therefore write private LDS partials that wave 0 sums in order.)
 // ------------------------------------------------------------------------------------
-constexpr unsigned long long kSpinLimit = 1ull << 24;  // ~1 s of polling per barrier
-
-// Sense-counting grid barrier.  bar[0] counts arrivals, bar[1] is the generation.  Every
-// wait is bounded: past kSpinLimit polls, or once any workgroup has timed out, the
-// workgroup records kStatusTimeout and proceeds, so the kernel always terminates.
-__device__ void grid_barrier(unsigned *bar, unsigned nblocks, unsigned &gen, unsigned *status) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned g = gen;
-        __threadfence();
-        unsigned prev = atomicAdd(&bar[0], 1u);
-        if (prev == nblocks - 1) {
-            atomicExch(&bar[0], 0u);
-            __threadfence();
-            __hip_atomic_store(&bar[1], g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit ||
-                    (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusTimeout)) {
-                    atomicOr(status, kStatusTimeout);
-                    break;
-                }
-            }
-        }
-        __threadfence();
-        gen = g + 1;
-    }
-    __syncthreads();
-}
-
-struct EmbedArgs {
-    float *Xc;          // caller coordinates: slot 0 of the iterate buffer, final result
-    float *Xw;          // workspace slot 1
+struct IterArgs {
+    float *Xc;          // caller coordinates: iterate slot 0, and the final result
+    float *Xw;          // workspace iterate slot 1
     float *G0;          // three gradient slots of n*d floats each
     float *P0;          // two partial slots of `units` floats each
-    double *loss_hist;  // sweeps entries, or nullptr
-    unsigned *bar;      // barrier words (zeroed before launch)
+    double *loss_hist;  // one entry per sweep, or nullptr
     unsigned *status;
     const int32_t *coo_row;
     const int32_t *col;
     long long nnz;
-    int n, d, nb, sweeps, iters, L, epu;  // epu: edge entries per unit
-    long long tiles, units_sweep, units;
+    int n, d, nb, epu;  // nb: 64-vertex blocks per side; epu: CSR entries per edge wave
+    long long units_edge, units;  // workgroups: [0, units_edge) edge work, then one per tile
     float neg_eta;
     PairParams P;
 };
 
+__device__ inline void reduce_loss(const IterArgs &a, int k, double *sh) {
+    double tot = block_sum_fixed(a.P0 + (size_t)(k & 1) * a.units, a.units, sh);
+    if (threadIdx.x == 0) {
+        a.loss_hist[k] = tot;
+        if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
+    }
+}
+
 template <int D>
-__global__ __launch_bounds__(256) void k_embed_persist(EmbedArgs a) {
+__global__ __launch_bounds__(256) void k_iter(IterArgs a, int k) {
     __shared__ double sh[kFinBlock];
+    __shared__ float rowp[4][64 * D];  // per-wave partials: plain LDS stores, summed in wave order
+    __shared__ float colp[4][64 * D];
+    __shared__ float wl[4];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const long long gwave = (long long)blockIdx.x * 4 + wave;
-    const long long nwaves = (long long)gridDim.x * 4;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int b = (int)blockIdx.x;
     const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nthreads = (long long)gridDim.x * blockDim.x;
     const long long nd = (long long)a.n * a.d;
-    const int dir = rot_dir(lane);
-    const int steps = 64 / a.L;
-    unsigned gen = 0;
     float *Xs[2] = {a.Xc, a.Xw};
+    const float *Xprev = (k == 0) ? a.Xc : Xs[(k - 1) & 1];
+    const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
+    float *Gk = a.G0 + (size_t)(k % 3) * nd;
+    float *Gnext = a.G0 + (size_t)((k + 1) % 3) * nd;
+    float *Pk = a.P0 + (size_t)(k & 1) * a.units;
+    const XView xv{Xprev, Gprev, a.neg_eta, a.d};
 
-    for (int k = 0; k < a.sweeps; ++k) {
-        const float *Xprev = (k == 0) ? Xs[0] : Xs[(k - 1) & 1];
-        const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
-        float *Gk = a.G0 + (size_t)(k % 3) * nd;
-        float *Gnext = a.G0 + (size_t)((k + 1) % 3) * nd;
-        float *Pk = a.P0 + (size_t)(k & 1) * a.units;
-        const XView xv{Xprev, Gprev, a.neg_eta, a.d};
-        // materialise x_k for the next iteration and clear the slot it will accumulate into
-        for (long long v = gtid; v < nd; v += nthreads) {
-            if (k > 0) Xs[k & 1][v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
-            Gnext[v] = 0.0f;
-        }
-        for (long long u = gwave; u < a.units; u += nwaves) {
-            float loss = 0.0f;
-            if (u < a.units_sweep) {
-                const long long t = u / steps;
-                const int s0 = (int)(u - t * steps) * a.L;
-                int I, J;
-                tile_of(t, a.nb, I, J);
-                const int i = I * 64 + lane;
-                const int col0 = J * 64;
-                const int jc = col0 + ((lane + dir * s0) & 63);
-                float xi[1][D], xc[D], gi[1][D], li[1], colacc[D];
-                int irow[1] = {i};
+    if (b == 0 && k > 0 && a.loss_hist) reduce_loss(a, k - 1, sh);
+    for (long long v = gtid; v < nd; v += nthreads) {
+        if (k > 0) Xs[k & 1][v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
+        Gnext[v] = 0.0f;
+    }
+    if (b >= a.units) return;  // uniform over the workgroup
+    float loss = 0.0f;
+    if (b < a.units_edge) {
+        // edge workgroups come first: their dependent gathers overlap the tiles
+        const long long e0 = ((long long)b * 4 + wave) * a.epu;
+        for (int q = 0; q < a.epu; q += 64) {
+            const long long e = e0 + q + lane;
+            int i = -1;
+            float dg[D];
 #pragma unroll
-                for (int k2 = 0; k2 < D; ++k2) {
-                    xi[0][k2] = (i < a.n && k2 < a.d) ? xv.at(i, k2) : 0.0f;
-                    xc[k2] = (jc < a.n && k2 < a.d) ? xv.at(jc, k2) : 0.0f;
-                    gi[0][k2] = 0.0f;
-                    colacc[k2] = 0.0f;
-                }
-                li[0] = 0.0f;
-                const bool masked = (I == J) || (col0 + 64 > a.n);
-                if (masked)
-                    sweep_steps<D, 1, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
-                                                   s0 + a.L, a.P);
-                else
-                    sweep_steps<D, 1, false, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
-                                                    s0 + a.L, a.P);
-                const int jf = col0 + ((lane + dir * (s0 + a.L)) & 63);
-                if (jf < a.n) {
+            for (int k2 = 0; k2 < D; ++k2) dg[k2] = 0.0f;
+            if (e < a.nnz) {
+                i = a.coo_row[e];
+                const int j = a.col[e];
+                const float ddl = edge_entry<D>(xv, i, j, dg, a.P);
+                if (i < j) loss += ddl;
+            }
 #pragma unroll
-                    for (int k2 = 0; k2 < D; ++k2)
-                        if (k2 < a.d) atomicAdd(&Gk[(size_t)jf * a.d + k2], -colacc[k2]);
-                }
-                if (i < a.n) {
-#pragma unroll
-                    for (int k2 = 0; k2 < D; ++k2)
-                        if (k2 < a.d) atomicAdd(&Gk[(size_t)i * a.d + k2], gi[0][k2]);
-                }
-            } else {
-                const long long e0 = (u - a.units_sweep) * (long long)a.epu;
-                for (int q = 0; q < a.epu; q += 64) {
-                    const long long e = e0 + q + lane;
-                    if (e < a.nnz) {
-                        const int i = a.coo_row[e];
-                        const int j = a.col[e];
-                        const float ddl = edge_entry<D>(xv, i, j, Gk, a.P);
-                        if (i < j) loss += ddl;
-                    }
+            for (int k2 = 0; k2 < D; ++k2) {
+                if (k2 < a.d) {
+                    float v = dg[k2];
+                    if (seg_sum_to_head(i, lane, v)) atomicAdd(&Gk[(size_t)i * a.d + k2], v);
                 }
             }
-            loss = wave_sum(loss);
-            if (lane == 0) Pk[u] = loss;
         }
-        // the FP64 loss of the previous sweep (its partials are complete): last workgroup
-        if (a.loss_hist && k > 0 && blockIdx.x == gridDim.x - 1) {
-            double tot = block_sum_fixed(a.P0 + (size_t)((k - 1) & 1) * a.units, a.units, sh);
-            if (threadIdx.x == 0) {
-                a.loss_hist[k - 1] = tot;
-                if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
+    } else {
+        // one 64 x 64 tile per workgroup; wave w runs steps [16 w, 16 w + 16) of the
+        // schedule, the four waves' row and column partials meet in LDS
+        const int dir = rot_dir(lane);
+        const int t = b - (int)a.units_edge;
+        int I, J;
+        tile_of(t, a.nb, I, J);
+        const int i = I * 64 + lane;
+        const int col0 = J * 64;
+        const int s0 = wave * 16;
+        const int jc = col0 + ((lane + dir * s0) & 63);
+        float xi[1][D], xc[D], gi[1][D], li[1], colacc[D];
+        int irow[1] = {i};
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            xi[0][q] = (i < a.n && q < a.d) ? xv.at(i, q) : 0.0f;
+            xc[q] = (jc < a.n && q < a.d) ? xv.at(jc, q) : 0.0f;
+            gi[0][q] = 0.0f;
+            colacc[q] = 0.0f;
+        }
+        li[0] = 0.0f;
+        if ((I == J) || (col0 + 64 > a.n))
+            sweep_steps<D, 1, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
+                                           a.P);
+        else
+            sweep_steps<D, 1, false, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
+                                            a.P);
+        const int cl = (lane + dir * (s0 + 15)) & 63;  // column whose partial this lane holds
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            rowp[wave][lane * D + q] = gi[0][q];
+            colp[wave][cl * D + q] = colacc[q];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const int jr = col0 + lane;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+                if (q < a.d) {
+                    const float rs = (rowp[0][lane * D + q] + rowp[1][lane * D + q]) +
+                                     (rowp[2][lane * D + q] + rowp[3][lane * D + q]);
+                    const float cs = (colp[0][lane * D + q] + colp[1][lane * D + q]) +
+                                     (colp[2][lane * D + q] + colp[3][lane * D + q]);
+                    if (i < a.n) atomicAdd(&Gk[(size_t)i * a.d + q], rs);
+                    if (jr < a.n) atomicAdd(&Gk[(size_t)jr * a.d + q], -cs);
+                }
             }
         }
-        grid_barrier(a.bar, gridDim.x, gen, a.status);
     }
-    const int K = a.sweeps;
-    if (K > 0 && a.loss_hist && blockIdx.x == gridDim.x - 1) {
-        double tot = block_sum_fixed(a.P0 + (size_t)((K - 1) & 1) * a.units, a.units, sh);
-        if (threadIdx.x == 0) {
-            a.loss_hist[K - 1] = tot;
-            if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
-        }
-    }
-    // final coordinates into the caller's buffer
-    if (a.iters > 0) {
-        if (K == a.iters + 1) {  // x_iters was materialised during the last sweep
-            if (a.iters & 1)
-                for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = a.Xw[v];
-        } else {  // K == iters: apply the last step now
-            const float *Xl = Xs[(a.iters - 1) & 1];
-            const float *Gl = a.G0 + (size_t)((a.iters - 1) % 3) * nd;
-            for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = __builtin_fmaf(a.neg_eta, Gl[v], Xl[v]);
-        }
+    loss = wave_sum(loss);
+    if (lane == 0) wl[wave] = loss;
+    __syncthreads();
+    if (threadIdx.x == 0) Pk[b] = (wl[0] + wl[1]) + (wl[2] + wl[3]);
+}
+
+// After K sweeps: the FP64 loss of the last sweep, and the final coordinates into the
+// caller's buffer (the last step applied now when no loss of the final iterate was asked).
+__global__ __launch_bounds__(256) void k_iter_finish(IterArgs a, int K, int iters) {
+    __shared__ double sh[kFinBlock];
+    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nthreads = (long long)gridDim.x * blockDim.x;
+    const long long nd = (long long)a.n * a.d;
+    if (blockIdx.x == 0 && K > 0 && a.loss_hist) reduce_loss(a, K - 1, sh);
+    if (iters <= 0) return;
+    if (K == iters + 1) {  // x_iters was written to slot iters&1 by the last sweep
+        if (iters & 1)
+            for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = a.Xw[v];
+    } else {
+        const float *Xl = (iters - 1) & 1 ? a.Xw : a.Xc;
+        const float *Gl = a.G0 + (size_t)((iters - 1) % 3) * nd;
+        for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = __builtin_fmaf(a.neg_eta, Gl[v], Xl[v]);
     }
 }
 
@@ -665,9 +687,8 @@ long long tiles_for(int n, int T) {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int kCUs = 256;                      // MI355X compute units
 constexpr long long kPersistMaxTiles = 65536;  // 64x64 tiles: n up to ~23k
-constexpr int kEdgesPerUnit = 256;
+constexpr int kEdgesPerUnit = 64;  // CSR entries per edge wave: one per lane
 
 }  // namespace
 
@@ -703,29 +724,15 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d) {
     p.edge_blocks = (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
 
-    // persistent plan: 64x64 tiles split into units of L steps, 2 waves per SIMD
+    // fused-iteration plan: one workgroup per 64x64 tile, edge workgroups first
     p.persist = false;
     const long long t64 = tiles_for(g->n, 64);
     if (p.D <= 16 && t64 <= kPersistMaxTiles) {
         p.persist = true;
         p.nb64 = (g->n + 63) / 64;
         p.tiles64 = t64;
-        p.p_grid = 2 * kCUs;  // workgroups of 4 independent waves
-        const long long waves = 4LL * p.p_grid;
-        p.units_edge = (g->nnz + kEdgesPerUnit - 1) / kEdgesPerUnit;
-        // pick the step range minimising the busiest wave's work (in steps, plus ~4 steps
-        // of per-unit overhead); an edge unit costs about as much as 8 steps
-        long long best = -1;
-        for (int L : {64, 32, 16, 8}) {
-            long long us = t64 * (64 / L);
-            long long per_wave = (us + p.units_edge + waves - 1) / waves;
-            long long cost = per_wave * (L + 4);
-            if (best < 0 || cost < best) {
-                best = cost;
-                p.L = L;
-            }
-        }
-        p.units_sweep = t64 * (64 / p.L);
+        p.units_edge = (g->nnz + 4 * kEdgesPerUnit - 1) / (4 * kEdgesPerUnit);
+        p.units_sweep = t64;
         p.units = p.units_sweep + p.units_edge;
     }
     return p;
@@ -755,9 +762,11 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
 
 PairParamsHost gempe_pair_params(const gempe_params *p) {
     PairParamsHost h;
-    h.mu = (float)p->mu;
+    const double d1s = -1.0 / (p->sigma * 0.69314718055994530942);  // -1 / (sigma ln 2)
+    h.mu_s = (float)(p->mu / p->sigma);
     h.inv_sigma = (float)(1.0 / p->sigma);
-    h.d1_scale = (float)(-1.0 / (p->sigma * 0.69314718055994530942));
+    h.c_neg = (float)(0.39894228040143267794 * d1s);  // sqrt(2/pi)/2
+    h.c_pos = (float)(0.39894228040143267794 * d1s);  // 1/sqrt(2 pi)
     return h;
 }
 
@@ -815,22 +824,12 @@ void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int
 }
 
 template <int D>
-hipError_t launch_persist(const SweepPlan &pl, EmbedArgs &a, hipStream_t s) {
-    static int max_blocks = -1;
-    if (max_blocks < 0) {
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_embed_persist<D>, 256, 0);
-        if (e != hipSuccess) return e;
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        max_blocks = per_cu * cus;
-    }
-    int grid = (int)std::min<long long>(pl.p_grid, max_blocks);
-    if (grid < 1) return hipErrorCooperativeLaunchTooLarge;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_embed_persist<D>), dim3(grid), dim3(256),
-                                      args, 0, s);
+void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_t s) {
+    const unsigned grid = (unsigned)std::max<long long>(1, pl.units);
+    for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_iter<D>, dim3(grid), dim3(256), 0, s, a, k);
+    const long long nd = (long long)a.n * a.d;
+    const unsigned fgrid = (unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256));
+    hipLaunchKernelGGL(k_iter_finish, dim3(fgrid), dim3(256), 0, s, a, K, iters);
 }
 
 }  // namespace
@@ -839,7 +838,7 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
                                   hipStream_t s, bool clear_status) {
-    PairParams P{pph.mu, pph.inv_sigma, pph.d1_scale};
+    PairParams P{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
     const int n = g->n;
     const long long nd = (long long)n * d;
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counters);
@@ -883,13 +882,12 @@ hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const Sw
                                          int iters, float eta, double *loss_hist, const WsLayout &L,
                                          unsigned char *ws, const PairParamsHost &pph, hipStream_t s) {
     const long long nd = (long long)g->n * d;
-    EmbedArgs a;
+    IterArgs a;
     a.Xc = X;
     a.Xw = reinterpret_cast<float *>(ws + L.xbuf);
     a.G0 = reinterpret_cast<float *>(ws + L.gring);
     a.P0 = reinterpret_cast<float *>(ws + L.ppart);
     a.loss_hist = loss_hist;
-    a.bar = reinterpret_cast<unsigned *>(ws + L.barrier);
     a.status = reinterpret_cast<unsigned *>(ws + L.counters + 8);
     a.coo_row = g->coo_row;
     a.col = g->col_idx;
@@ -897,27 +895,23 @@ hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const Sw
     a.n = g->n;
     a.d = d;
     a.nb = (int)plan.nb64;
-    a.iters = iters;
-    a.sweeps = iters + (loss_hist ? 1 : 0);
-    a.L = plan.L;
     a.epu = kEdgesPerUnit;
-    a.tiles = plan.tiles64;
-    a.units_sweep = plan.units_sweep;
+    a.units_edge = plan.units_edge;
     a.units = plan.units;
     a.neg_eta = -eta;
-    a.P = PairParams{pph.mu, pph.inv_sigma, pph.d1_scale};
-    // clear: gradient slot 0, barrier words and the status word (fill kernels, no memset)
+    a.P = PairParams{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
+    const int K = iters + (loss_hist ? 1 : 0);
+    // clear gradient slot 0 and the status word (a fill kernel, no memset)
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(ws + L.counters);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256))),
-                       dim3(256), 0, s, a.G0, nd, reinterpret_cast<float *>(ws + L.barrier), 64LL, cnt, 2);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+                       dim3(256), 0, s, a.G0, nd, nullptr, 0LL, cnt, 2);
     switch (plan.D) {
-        case 1: return launch_persist<1>(plan, a, s);
-        case 2: return launch_persist<2>(plan, a, s);
-        case 3: return launch_persist<3>(plan, a, s);
-        case 4: return launch_persist<4>(plan, a, s);
-        case 8: return launch_persist<8>(plan, a, s);
-        default: return launch_persist<16>(plan, a, s);
+        case 1: launch_iters<1>(plan, a, K, iters, s); break;
+        case 2: launch_iters<2>(plan, a, K, iters, s); break;
+        case 3: launch_iters<3>(plan, a, K, iters, s); break;
+        case 4: launch_iters<4>(plan, a, K, iters, s); break;
+        case 8: launch_iters<8>(plan, a, K, iters, s); break;
+        default: launch_iters<16>(plan, a, K, iters, s); break;
     }
+    return hipGetLastError();
 }
