@@ -61,9 +61,9 @@ gempe_status check_common(gempe_graph g, int32_t d, const gempe_params *p, const
             return gempe_fail(GEMPE_ERR_ARG, w + ": BF16_GRAM needs d >= 16 and d % 16 == 0");
         if (!(std::isfinite(p->near_k) && p->near_k > 0.0))
             return gempe_fail(GEMPE_ERR_ARG, w + ": near_k must be finite and > 0");
-        return gempe_fail(GEMPE_ERR_UNSUPPORTED, w + ": BF16_GRAM is not built into this library");
     }
-    if (p->precision != GEMPE_FP32) return gempe_fail(GEMPE_ERR_ARG, w + ": unknown precision");
+    if (p->precision != GEMPE_FP32 && p->precision != GEMPE_BF16_GRAM)
+        return gempe_fail(GEMPE_ERR_ARG, w + ": unknown precision");
     return GEMPE_OK;
 }
 
@@ -85,7 +85,7 @@ gempe_status check_ws(gempe_graph g, int32_t d, const void *ws, size_t ws_bytes,
 extern "C" size_t gempe_workspace_bytes(gempe_graph g, int32_t d, const gempe_params *p) {
     gempe_status st = check_common(g, d, p, "workspace_bytes");
     if (st != GEMPE_OK) return 0;
-    SweepPlan plan = gempe_make_plan(g, d);
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
     return gempe_ws_layout(g, d, plan).total;
 }
 
@@ -95,13 +95,14 @@ extern "C" gempe_status gempe_loss_grad(gempe_graph g, int32_t d, const float *X
     gempe_status st = check_common(g, d, p, "loss_grad");
     if (st != GEMPE_OK) return st;
     if (!X || !loss) return gempe_fail(GEMPE_ERR_ARG, "loss_grad: X and loss are required");
-    SweepPlan plan = gempe_make_plan(g, d);
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
     WsLayout L = gempe_ws_layout(g, d, plan);
     if ((st = check_ws(g, d, ws, ws_bytes, L, "loss_grad")) != GEMPE_OK) return st;
     unsigned char *w = static_cast<unsigned char *>(ws);
     float *G = grad ? grad : reinterpret_cast<float *>(w + L.gbuf);
     GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, row_loss, reinterpret_cast<float *>(w + L.partials),
-                                         w + L.counters, loss, edge_hits, gempe_pair_params(p), stream, true));
+                                         w + L.counters, loss, edge_hits, gempe_pair_params(p), stream, true,
+                                         gempe_gram_ctx(L, w, p)));
     return GEMPE_OK;
 }
 
@@ -111,7 +112,7 @@ extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta
     if (st != GEMPE_OK) return st;
     if (!X) return gempe_fail(GEMPE_ERR_ARG, "step: X is required");
     if (!(std::isfinite(eta) && eta > 0.0f)) return gempe_fail(GEMPE_ERR_ARG, "step: eta must be finite and > 0");
-    SweepPlan plan = gempe_make_plan(g, d);
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
     WsLayout L = gempe_ws_layout(g, d, plan);
     if ((st = check_ws(g, d, ws, ws_bytes, L, "step")) != GEMPE_OK) return st;
     unsigned char *w = static_cast<unsigned char *>(ws);
@@ -119,7 +120,8 @@ extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta
     // the loss lands in the workspace when the caller does not want it
     double *lossp = loss_before ? loss_before : reinterpret_cast<double *>(w + L.counters + 16);
     GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, reinterpret_cast<float *>(w + L.partials),
-                                         w + L.counters, lossp, nullptr, gempe_pair_params(p), stream, true));
+                                         w + L.counters, lossp, nullptr, gempe_pair_params(p), stream, true,
+                                         gempe_gram_ctx(L, w, p)));
     GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, (long long)g->n * d, stream));
     return GEMPE_OK;
 }
@@ -132,7 +134,7 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     if (!X) return gempe_fail(GEMPE_ERR_ARG, "embed: X is required");
     if (iters < 0) return gempe_fail(GEMPE_ERR_ARG, "embed: iters must be >= 0");
     if (!(std::isfinite(eta) && eta > 0.0f)) return gempe_fail(GEMPE_ERR_ARG, "embed: eta must be finite and > 0");
-    SweepPlan plan = gempe_make_plan(g, d);
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
     WsLayout L = gempe_ws_layout(g, d, plan);
     if ((st = check_ws(g, d, ws, ws_bytes, L, "embed")) != GEMPE_OK) return st;
     unsigned char *w = static_cast<unsigned char *>(ws);
@@ -141,6 +143,7 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     unsigned *status_ws = reinterpret_cast<unsigned *>(w + L.counters + 8);
     double *scratch_loss = reinterpret_cast<double *>(w + L.counters + 16);
     PairParamsHost pp = gempe_pair_params(p);
+    const GramCtx gc = gempe_gram_ctx(L, w, p);
     const long long nd = (long long)g->n * d;
     if (iters == 0 && !loss_hist) return GEMPE_OK;
     if (plan.persist) {
@@ -153,7 +156,7 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
             if (last && !loss_hist) break;
             double *lossp = loss_hist ? loss_hist + k : scratch_loss;
             GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr,
-                                                 pp, stream, k == 0));
+                                                 pp, stream, k == 0, gc));
             if (!last) GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, nd, stream));
         }
     }

@@ -95,6 +95,9 @@ struct SweepPlan {
     long long nb64 = 0;        // 64-vertex blocks per side
     long long tiles64 = 0;     // upper-triangle 64x64 tiles
     long long units_sweep = 0, units_edge = 0, units = 0;  // workgroups per iteration
+    // BF16 Gram screen (precision GEMPE_BF16_GRAM): items = 64x64 upper tiles, D = padded
+    // dimension of the exact pass over the flagged tiles
+    bool bf16 = false;
 };
 
 struct WsLayout {
@@ -104,11 +107,17 @@ struct WsLayout {
     size_t xbuf = 0;      // float[n*d] embed: second slot of the double-buffered iterate
     size_t gring = 0;     // float[3*n*d] embed: three gradient slots
     size_t ppart = 0;     // float[2*plan.units] embed: double-buffered loss partials
-    size_t barrier = 0;   // 256 B: grid barrier counter + generation
+    size_t barrier = 0;   // 256 B (reserved)
+    // BF16 Gram screen
+    size_t xb = 0;        // bf16[n*d] rounded coordinates
+    size_t nrm = 0;       // float[n] squared norms of the rounded coordinates
+    size_t snorm = 0;     // float[n] norms of the coordinates
+    size_t flags = 0;     // uint8[items] near flags of the 64x64 tiles
+    size_t list = 0;      // int32[items] flagged tiles in order
     size_t total = 0;
 };
 
-SweepPlan gempe_make_plan(const gempe_graph_s *g, int d);
+SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16);
 WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 
 // Kernel launchers (sweep.hip).
@@ -117,10 +126,24 @@ struct PairParamsHost {
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 
+// Workspace pointers and threshold of the BF16 Gram screen (unused for FP32 plans).
+struct GramCtx {
+    void *xb = nullptr;
+    float *nrm = nullptr, *snorm = nullptr;
+    unsigned char *flags = nullptr;
+    int *list = nullptr, *count = nullptr;
+    float theta0 = 0.0f;  // mu + near_k sigma
+};
+GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p);
+
 hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                   const float *X, float *grad, float *row_loss, float *partials,
                                   unsigned char *counters, double *loss, int64_t *hits_out,
-                                  const PairParamsHost &pp, hipStream_t s, bool clear_status);
+                                  const PairParamsHost &pp, hipStream_t s, bool clear_status,
+                                  const GramCtx &gc);
+hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
+                                    float *snorm, unsigned char *flags, int *list, int *count, float theta0,
+                                    hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                          float *X, int iters, float eta, double *loss_hist,

@@ -272,25 +272,20 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// LDS-resident sweep for wide embeddings (d in 17..128), one wave per workgroup, T = 64.
+// LDS-resident sweep for wide embeddings (d in 17..128, and the exact pass of the BF16
+// screen), one wave per workgroup, tiles of 64 x 64.
 // ------------------------------------------------------------------------------------
 template <int D, bool ROWLOSS>
-__global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, int n, int d, int nt,
-                                                   long long items, long long per_xcd,
-                                                   float *__restrict__ G, float *__restrict__ rowloss,
-                                                   float *__restrict__ partials, PairParams P) {
+__device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int J, float *__restrict__ G,
+                           float *__restrict__ rowloss, const PairParams &P, float *lds) {
     constexpr int S = D + 1;  // padded stride: lane-private rows hit distinct banks
-    extern __shared__ float lds[];
     float *xr = lds;           // rows    [64][S]
     float *gr = xr + 64 * S;   // row gradients
     float *xc = gr + 64 * S;   // columns
     float *gc = xc + 64 * S;   // column gradients
     const int lane = threadIdx.x;
-    const long long t = xcd_item(blockIdx.x, per_xcd);
-    if (t >= items) return;
-    int I, J;
-    tile_of(t, nt, I, J);
     const int i = I * 64 + lane;
+    __syncthreads();  // the previous tile's LDS contents are consumed
     for (int k = lane; k < 64 * S; k += 64) {
         int c = k / S, dd = k - c * S;
         int ri = I * 64 + c, cj = J * 64 + c;
@@ -346,8 +341,38 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
         }
     }
     if (ROWLOSS && i < n) atomicAdd(&rowloss[i], lrow);
-    float wsum = wave_sum(loss);
-    if (lane == 0) partials[t] = wsum;
+    return wave_sum(loss);
+}
+
+template <int D, bool ROWLOSS>
+__global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, int n, int d, int nt,
+                                                   long long items, long long per_xcd,
+                                                   float *__restrict__ G, float *__restrict__ rowloss,
+                                                   float *__restrict__ partials, PairParams P) {
+    extern __shared__ float lds[];
+    const long long t = xcd_item(blockIdx.x, per_xcd);
+    if (t >= items) return;
+    int I, J;
+    tile_of(t, nt, I, J);
+    float l = wide_tile<D, ROWLOSS>(X, n, d, I, J, G, rowloss, P, lds);
+    if (threadIdx.x == 0) partials[t] = l;
+}
+
+// Exact FP32 pass over the tiles the BF16 screen flagged: list[0..*count) holds upper-
+// triangle 64 x 64 tile indices in increasing order; partial slot q belongs to list[q].
+template <int D, bool ROWLOSS>
+__global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict__ X, int n, int d, int nt,
+                                                        const int *__restrict__ list, const int *__restrict__ count,
+                                                        float *__restrict__ G, float *__restrict__ rowloss,
+                                                        float *__restrict__ partials, PairParams P) {
+    extern __shared__ float lds[];
+    const int cnt = *count;
+    for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+        int I, J;
+        tile_of(list[q], nt, I, J);
+        float l = wide_tile<D, ROWLOSS>(X, n, d, I, J, G, rowloss, P, lds);
+        if (threadIdx.x == 0) partials[q] = l;
+    }
 }
 
 // ------------------------------------------------------------------------------------
@@ -692,8 +717,22 @@ constexpr int kEdgesPerUnit = 64;  // CSR entries per edge wave: one per lane
 
 }  // namespace
 
-SweepPlan gempe_make_plan(const gempe_graph_s *g, int d) {
+SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
     SweepPlan p;
+    if (bf16) {
+        // screen on 128x128 tiles, exact FP32 pass over flagged 64x64 tiles (LDS kernel)
+        p.bf16 = true;
+        p.D = d <= 16 ? 16 : d <= 32 ? 32 : d <= 64 ? 64 : 128;
+        p.R = 1;
+        p.W = 1;
+        p.T = 64;
+        p.nt = (g->n + 63) / 64;
+        p.items = (long long)p.nt * (p.nt + 1) / 2;
+        p.grid = std::min<long long>(p.items, 2048);
+        p.edge_blocks = (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
+        p.partials = p.items + p.edge_blocks;
+        return p;
+    }
     p.D = padded_dim(d);
     if (p.D <= 16) {
         // largest tiles that still give >= 8 waves per SIMD (256 CUs x 4 SIMDs)
@@ -756,8 +795,33 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     off = align256(off + sizeof(float) * 2 * (size_t)std::max<long long>(plan.units, 1));
     L.barrier = off;
     off += 256;
+    if (plan.bf16) {
+        L.xb = off;
+        off = align256(off + 2 * nd);
+        L.nrm = off;
+        off = align256(off + sizeof(float) * (size_t)g->n);
+        L.snorm = off;
+        off = align256(off + sizeof(float) * (size_t)g->n);
+        L.flags = off;
+        off = align256(off + (size_t)plan.items);
+        L.list = off;
+        off = align256(off + sizeof(int) * (size_t)plan.items);
+    }
     L.total = off;
     return L;
+}
+
+GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p) {
+    GramCtx c;
+    if (!L.xb) return c;
+    c.xb = ws + L.xb;
+    c.nrm = reinterpret_cast<float *>(ws + L.nrm);
+    c.snorm = reinterpret_cast<float *>(ws + L.snorm);
+    c.flags = ws + L.flags;
+    c.list = reinterpret_cast<int *>(ws + L.list);
+    c.count = reinterpret_cast<int *>(ws + L.counters + 32);
+    c.theta0 = (float)(p->mu + p->near_k * p->sigma);
+    return c;
 }
 
 PairParamsHost gempe_pair_params(const gempe_params *p) {
@@ -807,6 +871,31 @@ void launch_wide(const SweepPlan &pl, hipStream_t s, const float *X, int n, int 
                        pl.items, per, G, rl, part, P);
 }
 
+template <int D, bool RL>
+void launch_wide_list(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, const GramCtx &gc,
+                      float *G, float *rl, float *part, PairParams P) {
+    size_t lds = sizeof(float) * 4 * 64 * (D + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide_list<D, RL>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_sweep_wide_list<D, RL>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
+                       gc.list, gc.count, G, rl, part, P);
+}
+
+template <bool RL>
+void launch_list(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, const GramCtx &gc, float *G,
+                 float *rl, float *part, PairParams P) {
+    switch (pl.D) {
+        case 16: return launch_wide_list<16, RL>(pl, s, X, n, d, gc, G, rl, part, P);
+        case 32: return launch_wide_list<32, RL>(pl, s, X, n, d, gc, G, rl, part, P);
+        case 64: return launch_wide_list<64, RL>(pl, s, X, n, d, gc, G, rl, part, P);
+        default: return launch_wide_list<128, RL>(pl, s, X, n, d, gc, G, rl, part, P);
+    }
+}
+
 template <bool RL>
 void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, float *G, float *rl,
                   float *part, PairParams P) {
@@ -837,7 +926,7 @@ void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_
 hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X,
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
-                                  hipStream_t s, bool clear_status) {
+                                  hipStream_t s, bool clear_status, const GramCtx &gc) {
     PairParams P{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
     const int n = g->n;
     const long long nd = (long long)n * d;
@@ -849,10 +938,22 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
         hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, grad, nd, row_loss, row_loss ? (long long)n : 0,
                            cnt, clear_status ? 2 : 1);
     }
-    if (row_loss)
+    if (plan.bf16) {
+        // loss slots of unflagged tiles stay 0
+        unsigned pb = (unsigned)std::min<long long>(4096, std::max<long long>(1, (plan.items + 255) / 256));
+        hipLaunchKernelGGL(k_zero, dim3(pb), dim3(256), 0, s, partials, plan.items, nullptr, 0LL, nullptr, 0);
+        hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.flags, gc.list, gc.count,
+                                                gc.theta0, s);
+        if (e != hipSuccess) return e;
+        if (row_loss)
+            launch_list<true>(plan, s, X, n, d, gc, grad, row_loss, partials, P);
+        else
+            launch_list<false>(plan, s, X, n, d, gc, grad, row_loss, partials, P);
+    } else if (row_loss) {
         launch_sweep<true>(plan, s, X, n, d, grad, row_loss, partials, P);
-    else
+    } else {
         launch_sweep<false>(plan, s, X, n, d, grad, row_loss, partials, P);
+    }
     float *epart = partials + plan.items;
     if (g->nnz > 0) {
         if (row_loss)

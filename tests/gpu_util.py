@@ -19,6 +19,10 @@ from paper_2011_03479_amd import gempe
 LOSS_RTOL = 1e-5
 GRAD_RTOL = 1e-4
 GRAD_FLOOR = 1e-2
+# BF16 Gram screen: the stated looser bound (the flushed far pairs themselves are below
+# 2e-19 bits each; the bound leaves room for the screen's conservative choices)
+BF16_LOSS_RTOL = 1e-4
+BF16_GRAD_RTOL = 1e-3
 
 
 def note(msg: str):
@@ -66,27 +70,29 @@ def assert_loss_close(loss, ref, rtol=LOSS_RTOL, what=""):
     assert abs(loss - ref) <= rtol * abs(ref), f"{what}: loss {loss!r} vs oracle {ref!r} (rel {abs(loss-ref)/abs(ref):.3g})"
 
 
-def check_full(graph, G, X, mu=1.5, sigma=1.0, params=None, row_loss=True, what=""):
+def check_full(graph, G, X, mu=1.5, sigma=1.0, params=None, row_loss=True, what="", loss_rtol=LOSS_RTOL,
+               grad_rtol=GRAD_RTOL):
     """Whole-graph parity: loss, every vertex's gradient, edge hits, row losses."""
     got = gpu_loss_grad(G, X, params=params, row_loss=row_loss)
     ref = oracle.loss_grad(X, graph.row_ptr, graph.col_idx, mu, sigma, want_row_loss=True, want_abs_slope=True)
     assert got["edge_hits"] == graph.m == ref["edge_hits"], (what, got["edge_hits"], graph.m)
-    assert_loss_close(got["loss"], ref["loss"], what=what)
-    assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], what=what)
+    assert_loss_close(got["loss"], ref["loss"], rtol=loss_rtol, what=what)
+    assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], rtol=grad_rtol, what=what)
     if row_loss:
         rl = got["row_loss"]
-        assert np.all(np.abs(rl - ref["row_loss"]) <= 1e-5 * np.abs(ref["row_loss"]) + 1e-6), what
+        assert np.all(np.abs(rl - ref["row_loss"]) <= loss_rtol * np.abs(ref["row_loss"]) + 1e-6), what
     return got, ref
 
 
-def check_rows(graph, G, X, rows, mu=1.5, sigma=1.0, params=None, what=""):
+def check_rows(graph, G, X, rows, mu=1.5, sigma=1.0, params=None, what="", loss_rtol=LOSS_RTOL,
+               grad_rtol=GRAD_RTOL):
     """Sampled-row parity for sizes the oracle cannot sweep whole."""
     got = gpu_loss_grad(G, X, params=params, row_loss=True)
     ref = oracle.rows(X, graph.row_ptr, graph.col_idx, rows, mu, sigma)
     assert got["edge_hits"] == graph.m, (what, got["edge_hits"], graph.m)
-    assert_grad_close(got["grad"][rows], ref["grad"], ref["abs_slope"], what=what)
+    assert_grad_close(got["grad"][rows], ref["grad"], ref["abs_slope"], rtol=grad_rtol, what=what)
     rl = got["row_loss"][rows]
-    assert np.all(np.abs(rl - ref["row_loss"]) <= 1e-5 * np.abs(ref["row_loss"]) + 1e-6), what
+    assert np.all(np.abs(rl - ref["row_loss"]) <= loss_rtol * np.abs(ref["row_loss"]) + 1e-6), what
     # the loss is half the sum of the row losses (self-consistency at full size)
     half = 0.5 * float(np.sum(got["row_loss"]))
     assert abs(half - got["loss"]) <= 1e-5 * got["loss"], (what, half, got["loss"])

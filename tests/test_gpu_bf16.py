@@ -1,0 +1,104 @@
+"""BF16 MFMA Gram screen (precision GEMPE_BF16_GRAM) against the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import (BF16_GRAD_RTOL, BF16_LOSS_RTOL, check_full, check_rows, gpu_loss_grad, note, require_gpu,
+                      to_dev)
+from paper_2011_03479_amd import gempe, synth
+
+pytestmark = pytest.mark.gpu
+
+BF16 = dict(precision=1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+    oracle.build(force=False)
+
+
+def clusters(n, d, k, spread, sep, seed):
+    """k cluster centres `sep` apart (pairwise far), points N(0, spread^2) around them."""
+    rng = np.random.default_rng(seed)
+    centres = rng.standard_normal((k, d)) * sep
+    lab = rng.integers(0, k, n)
+    return (centres[lab] + rng.standard_normal((n, d)) * spread).astype(np.float32), lab
+
+
+@pytest.mark.parametrize("n,d", [(700, 64), (257, 16), (130, 128), (1000, 48)])
+def test_bf16_all_near_equals_fp32_bound(n, d):
+    """Contracted embedding (typical delta ~ mu): every tile is flagged, the exact FP32
+    pass covers everything, so the FP32 bound holds."""
+    g = synth.erdos_renyi(n, 8.0, seed=n + d)
+    X = synth.init_embedding(n, d, seed=5 * n + d, scale=1.5 / np.sqrt(2 * d))
+    note(f"bf16 all-near n={n} d={d}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    check_full(g, G, X, params=gempe.params_default(**BF16), what=f"bf16 near n{n} d{d}")
+
+
+@pytest.mark.parametrize("n,d", [(3000, 128), (1200, 64), (333, 32)])
+def test_bf16_far_init(n, d):
+    """N(0,1) init: all non-edge pairs far, only edges matter."""
+    g = synth.sbm(6, n // 6, 0.02, 0.001, seed=n)
+    n = g.n
+    X = synth.init_embedding(n, d, seed=n + 7)
+    note(f"bf16 far n={n} d={d}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    check_full(g, G, X, params=gempe.params_default(**BF16), what=f"bf16 far n{n} d{d}",
+               loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL)
+
+
+@pytest.mark.parametrize("n,d", [(1500, 64), (900, 128)])
+def test_bf16_clusters_mixed(n, d):
+    """Tight clusters far apart: within-cluster tiles are flagged, cross-cluster pairs flushed."""
+    X, lab = clusters(n, d, 6, spread=0.12, sep=4.0, seed=n)
+    # edges mostly inside clusters
+    rng = np.random.default_rng(n)
+    u = rng.integers(0, n, 8 * n)
+    v = np.where(rng.random(8 * n) < 0.9, u, rng.integers(0, n, 8 * n))
+    same = np.array([rng.choice(np.nonzero(lab == lab[a])[0]) for a in u[:4 * n]])
+    uu = np.concatenate([u[:4 * n], u[4 * n:]])
+    vv = np.concatenate([same, v[4 * n:]])
+    g = synth.csr_from_edges(n, uu, vv)
+    note(f"bf16 clusters n={n} d={d} m={g.m}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    got, ref = check_full(g, G, X, params=gempe.params_default(**BF16), what=f"bf16 clusters n{n} d{d}",
+                          loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL)
+    # the flushed pairs are negligible: the result is in fact FP32-accurate
+    assert abs(got["loss"] - ref["loss"]) <= 1e-5 * ref["loss"]
+
+
+def test_bf16_embed_trajectory():
+    n, d, iters = 1024, 64, 3
+    g = synth.chung_lu(n, 10.0, 2.5, seed=3)
+    X0 = synth.init_embedding(n, d, seed=9, scale=0.2)
+    eta = 0.1 / (n - 1)
+    note("bf16 embed n=1024 d=64 iters=3")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    p = gempe.params_default(**BF16)
+    ws = gempe.workspace(G, d, p)
+    X = to_dev(X0)
+    hist = torch.empty(iters + 1, dtype=torch.float64, device="cuda")
+    gempe.embed(G, X, iters, eta, ws=ws, params=p, loss_hist=hist)
+    ref_hist, X_ref = oracle.gd_trajectory(X0, g.row_ptr, g.col_idx, iters, eta)
+    assert np.allclose(hist.cpu().numpy(), ref_hist, rtol=BF16_LOSS_RTOL, atol=0)
+    xg = X.double().cpu().numpy()
+    assert np.max(np.linalg.norm(xg - X_ref, axis=1)) <= 1e-3 * np.max(np.linalg.norm(X_ref, axis=1))
+
+
+def test_sbm100k_sampled_rows():
+    """The representation-learning workload at full size (n = 100,000, d = 128, SBM 50 x
+    2,000): sampled rows against the oracle, every edge counted once."""
+    w = synth.workload("sbm100k")
+    g = w.graph
+    rng = np.random.default_rng(0)
+    hubs = np.argsort(-np.diff(g.row_ptr))[:8]
+    rows = np.unique(np.concatenate([rng.choice(g.n, 150, replace=False), hubs, [0, g.n - 1]]))
+    note(f"sbm100k sampled rows, m={g.m}")
+    G = gempe.Graph(g.n, g.row_ptr, g.col_idx)
+    check_rows(g, G, w.X0, rows, params=gempe.params_default(**BF16), what="sbm100k",
+               loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL)
