@@ -102,7 +102,7 @@ extern "C" gempe_status gempe_loss_grad(gempe_graph g, int32_t d, const float *X
     float *G = grad ? grad : reinterpret_cast<float *>(w + L.gbuf);
     GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, row_loss, reinterpret_cast<float *>(w + L.partials),
                                          w + L.counters, loss, edge_hits, gempe_pair_params(p), stream, true,
-                                         gempe_gram_ctx(L, w, p)));
+                                         gempe_gram_ctx(L, w, p), reinterpret_cast<double *>(w + L.red)));
     return GEMPE_OK;
 }
 
@@ -121,7 +121,7 @@ extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta
     double *lossp = loss_before ? loss_before : reinterpret_cast<double *>(w + L.counters + 16);
     GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, reinterpret_cast<float *>(w + L.partials),
                                          w + L.counters, lossp, nullptr, gempe_pair_params(p), stream, true,
-                                         gempe_gram_ctx(L, w, p)));
+                                         gempe_gram_ctx(L, w, p), reinterpret_cast<double *>(w + L.red)));
     GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, (long long)g->n * d, stream));
     return GEMPE_OK;
 }
@@ -156,7 +156,7 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
             if (last && !loss_hist) break;
             double *lossp = loss_hist ? loss_hist + k : scratch_loss;
             GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr,
-                                                 pp, stream, k == 0, gc));
+                                                 pp, stream, k == 0, gc, reinterpret_cast<double *>(w + L.red)));
             if (!last) GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, nd, stream));
         }
     }

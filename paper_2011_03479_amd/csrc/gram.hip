@@ -187,18 +187,35 @@ __global__ __launch_bounds__(256) void k_gram_screen(const __bf16 *__restrict__ 
 
 // Ordered compaction of the flags: list[0..count) = indices of flagged 64 x 64 tiles in
 // increasing order (deterministic tile order for the exact pass and its loss partials).
+// Thread t owns a contiguous range of 16-byte words; all-zero words (the common case) are
+// skipped with one compare.  The flag region is 16-byte aligned; bytes past `total` are
+// ignored.
 constexpr int kCompactThreads = 1024;
+
+__device__ __forceinline__ int flags_in_word(const uint4 &w, long long base, long long total) {
+    int c = 0;
+    const unsigned v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        c += (base + q < total && ((v[q >> 2] >> (8 * (q & 3))) & 0xffu)) ? 1 : 0;
+    return c;
+}
 
 __global__ __launch_bounds__(kCompactThreads) void k_compact(const unsigned char *__restrict__ flags,
                                                              long long total, int *__restrict__ list,
                                                              int *__restrict__ count) {
     __shared__ int scan[kCompactThreads];
     const int tid = threadIdx.x;
-    const long long chunk = (total + kCompactThreads - 1) / kCompactThreads;
-    const long long lo = std::min<long long>(total, (long long)tid * chunk);
-    const long long hi = std::min<long long>(total, lo + chunk);
+    const uint4 *fw = reinterpret_cast<const uint4 *>(flags);
+    const long long nw = (total + 15) / 16;
+    const long long chunk = (nw + kCompactThreads - 1) / kCompactThreads;
+    const long long lo = std::min<long long>(nw, (long long)tid * chunk);
+    const long long hi = std::min<long long>(nw, lo + chunk);
     int c = 0;
-    for (long long q = lo; q < hi; ++q) c += flags[q] ? 1 : 0;
+    for (long long q = lo; q < hi; ++q) {
+        uint4 w = fw[q];
+        if (w.x | w.y | w.z | w.w) c += flags_in_word(w, q * 16, total);
+    }
     scan[tid] = c;
     __syncthreads();
     for (int off = 1; off < kCompactThreads; off <<= 1) {  // inclusive Hillis-Steele scan
@@ -208,8 +225,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(const unsigned char
         __syncthreads();
     }
     int pos = scan[tid] - c;
-    for (long long q = lo; q < hi; ++q)
-        if (flags[q]) list[pos++] = (int)q;
+    for (long long q = lo; q < hi; ++q) {
+        uint4 w = fw[q];
+        if (!(w.x | w.y | w.z | w.w)) continue;
+        const unsigned v[4] = {w.x, w.y, w.z, w.w};
+        for (int b = 0; b < 16; ++b)
+            if (q * 16 + b < total && ((v[b >> 2] >> (8 * (b & 3))) & 0xffu)) list[pos++] = (int)(q * 16 + b);
+    }
     if (tid == kCompactThreads - 1) *count = scan[tid];
 }
 

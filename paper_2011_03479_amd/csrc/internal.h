@@ -108,6 +108,7 @@ struct WsLayout {
     size_t gring = 0;     // float[3*n*d] embed: three gradient slots
     size_t ppart = 0;     // float[2*plan.units] embed: double-buffered loss partials
     size_t barrier = 0;   // 256 B (reserved)
+    size_t red = 0;       // double[1024] first level of the FP64 loss reduction
     // BF16 Gram screen
     size_t xb = 0;        // bf16[n*d] rounded coordinates
     size_t nrm = 0;       // float[n] squared norms of the rounded coordinates
@@ -140,7 +141,7 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   const float *X, float *grad, float *row_loss, float *partials,
                                   unsigned char *counters, double *loss, int64_t *hits_out,
                                   const PairParamsHost &pp, hipStream_t s, bool clear_status,
-                                  const GramCtx &gc);
+                                  const GramCtx &gc, double *red);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, unsigned char *flags, int *list, int *count, float theta0,
                                     hipStream_t s);

@@ -476,6 +476,66 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     }
 }
 
+// Exact edge correction for wide embeddings (d > 16): one wave per CSR row, lanes over
+// coordinates (two per lane), so coordinate loads are coalesced and the row's gradient
+// change stays in registers until one atomic per coordinate.  The squared distance is a
+// wave-wide sum, so it agrees with the sweep's sequential sum to rounding (not bitwise);
+// the residual is a relative 1e-7 of dl- for that edge.
+template <bool ROWLOSS>
+__global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X, int n, int d,
+                                                    const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const unsigned long long *__restrict__ table,
+                                                    unsigned long long cap, float *__restrict__ G,
+                                                    float *__restrict__ rowloss, float *__restrict__ partials,
+                                                    unsigned long long *hits, PairParams P) {
+    __shared__ float wsum[4];
+    __shared__ unsigned whit[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
+    float dloss = 0.0f;
+    unsigned hitc = 0;
+    if (i < n) {
+        const float *xi = X + (size_t)i * d;
+        const float xi0 = lane < d ? xi[lane] : 0.0f;
+        const float xi1 = lane + 64 < d ? xi[lane + 64] : 0.0f;
+        float g0 = 0.0f, g1 = 0.0f, lrow = 0.0f;
+        const long long e1 = row_ptr[i + 1];
+        for (long long e = row_ptr[i]; e < e1; ++e) {
+            const int j = col[e];
+            const float *xj = X + (size_t)j * d;
+            const float df0 = xi0 - (lane < d ? xj[lane] : 0.0f);
+            const float df1 = xi1 - (lane + 64 < d ? xj[lane + 64] : 0.0f);
+            const float r2 = wave_sum(__builtin_fmaf(df1, df1, df0 * df0));
+            float dlp, ccp, dln, ccn;
+            pair_eval(r2, -1.0f, P, dlp, ccp);
+            pair_eval(r2, 1.0f, P, dln, ccn);
+            const float dcc = ccp - ccn;
+            g0 += dcc * df0;
+            g1 += dcc * df1;
+            const float ddl = dlp - dln;
+            if (ROWLOSS) lrow += ddl;
+            if (i < j) {
+                dloss += ddl;
+                if (lane == 0 && gempe_hash_contains(table, cap, gempe_edge_key(i, j))) ++hitc;
+            }
+        }
+        if (lane < d) atomicAdd(&G[(size_t)i * d + lane], g0);
+        if (lane + 64 < d) atomicAdd(&G[(size_t)i * d + lane + 64], g1);
+        if (ROWLOSS && lane == 0) atomicAdd(&rowloss[i], lrow);
+    }
+    if (lane == 0) {
+        wsum[wave] = dloss;
+        whit[wave] = hitc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        unsigned h = whit[0] + whit[1] + whit[2] + whit[3];
+        if (h) atomicAdd(hits, (unsigned long long)h);
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // Small kernels: zero fill, FP64 fixed-order loss reduction, X -= eta G.
 // ------------------------------------------------------------------------------------
@@ -506,16 +566,45 @@ __device__ inline double block_sum_fixed(const float *__restrict__ partials, lon
     return sh[0];
 }
 
-__global__ __launch_bounds__(kFinBlock) void k_finalize(const float *__restrict__ partials,
-                                                        long long count, double *loss,
-                                                        const unsigned long long *hits,
-                                                        int64_t *hits_out, unsigned *status) {
+// Two-level FP64 sum of the loss partials, deterministic: the partials are the
+// concatenation p1[0..m1) ++ p2[0..n2), m1 = *n1_dev when given (a device-side count) else
+// n1; block b of the first level sums the fixed slot range [b chunk, (b + 1) chunk).
+__global__ __launch_bounds__(kFinBlock) void k_reduce1(const float *__restrict__ p1, long long n1,
+                                                       const int *__restrict__ n1_dev,
+                                                       const float *__restrict__ p2, long long n2,
+                                                       long long chunk, double *__restrict__ out) {
     __shared__ double sh[kFinBlock];
-    double tot = block_sum_fixed(partials, count, sh);
+    const long long m1 = n1_dev ? (long long)*n1_dev : n1;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = std::min(lo + chunk, m1 + n2);
+    double acc = 0.0;
+    for (long long q = lo + threadIdx.x; q < hi; q += kFinBlock)
+        acc += (double)(q < m1 ? p1[q] : p2[q - m1]);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kFinBlock / 2; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const double *__restrict__ part, int nb, double *loss,
+                                                        const unsigned long long *hits, int64_t *hits_out,
+                                                        unsigned *status) {
+    __shared__ double sh[kFinBlock];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nb; q += kFinBlock) acc += part[q];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kFinBlock / 2; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        *loss = tot;
+        *loss = sh[0];
         if (hits_out) *hits_out = (int64_t)*hits;
-        if (!isfinite(tot)) atomicOr(status, kStatusNonFinite);
+        if (!isfinite(sh[0])) atomicOr(status, kStatusNonFinite);
     }
 }
 
@@ -713,7 +802,8 @@ long long tiles_for(int n, int T) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr long long kPersistMaxTiles = 65536;  // 64x64 tiles: n up to ~23k
-constexpr int kEdgesPerUnit = 64;  // CSR entries per edge wave: one per lane
+constexpr int kEdgesPerUnit = 64;
+constexpr int kRed1Blocks = 1024;  // first level of the FP64 loss reduction  // CSR entries per edge wave: one per lane
 
 }  // namespace
 
@@ -729,7 +819,7 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
         p.nt = (g->n + 63) / 64;
         p.items = (long long)p.nt * (p.nt + 1) / 2;
         p.grid = std::min<long long>(p.items, 2048);
-        p.edge_blocks = (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
+        p.edge_blocks = (int)std::max<long long>(1, ((long long)g->n + 3) / 4);  // one wave per row
         p.partials = p.items + p.edge_blocks;
         return p;
     }
@@ -760,7 +850,8 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
     p.items = (long long)p.nt * (p.nt + 1) / 2;
     long long per = (p.items + kXcd - 1) / kXcd;
     p.grid = per * kXcd;
-    p.edge_blocks = (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
+    p.edge_blocks = p.D > 16 ? (int)std::max<long long>(1, ((long long)g->n + 3) / 4)
+                             : (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
 
     // fused-iteration plan: one workgroup per 64x64 tile, edge workgroups first
@@ -795,6 +886,8 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     off = align256(off + sizeof(float) * 2 * (size_t)std::max<long long>(plan.units, 1));
     L.barrier = off;
     off += 256;
+    L.red = off;
+    off = align256(off + sizeof(double) * kRed1Blocks);
     if (plan.bf16) {
         L.xb = off;
         off = align256(off + 2 * nd);
@@ -926,7 +1019,7 @@ void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_
 hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X,
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
-                                  hipStream_t s, bool clear_status, const GramCtx &gc) {
+                                  hipStream_t s, bool clear_status, const GramCtx &gc, double *red) {
     PairParams P{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
     const int n = g->n;
     const long long nd = (long long)n * d;
@@ -939,9 +1032,6 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                            cnt, clear_status ? 2 : 1);
     }
     if (plan.bf16) {
-        // loss slots of unflagged tiles stay 0
-        unsigned pb = (unsigned)std::min<long long>(4096, std::max<long long>(1, (plan.items + 255) / 256));
-        hipLaunchKernelGGL(k_zero, dim3(pb), dim3(256), 0, s, partials, plan.items, nullptr, 0LL, nullptr, 0);
         hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.flags, gc.list, gc.count,
                                                 gc.theta0, s);
         if (e != hipSuccess) return e;
@@ -955,7 +1045,15 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
         launch_sweep<false>(plan, s, X, n, d, grad, row_loss, partials, P);
     }
     float *epart = partials + plan.items;
-    if (g->nnz > 0) {
+    if (plan.D > 16) {
+        // wide: one wave per CSR row (also writes the partial of rows without edges)
+        if (row_loss)
+            hipLaunchKernelGGL((k_edges_rows<true>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
+                               g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, row_loss, epart, cnt, P);
+        else
+            hipLaunchKernelGGL((k_edges_rows<false>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
+                               g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, row_loss, epart, cnt, P);
+    } else if (g->nnz > 0) {
         if (row_loss)
             hipLaunchKernelGGL((k_edges<true>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
                                g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad,
@@ -968,8 +1066,13 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
         hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, epart, (long long)plan.edge_blocks, nullptr, 0LL,
                            nullptr, 0);
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, s, partials, plan.partials, loss, cnt,
-                       hits_out, status);
+    // FP64 loss: sweep partials (for the BF16 screen only the flagged tiles' slots) + edge partials
+    const long long total = plan.items + plan.edge_blocks;
+    const int nb1 = (int)std::min<long long>(kRed1Blocks, std::max<long long>(1, (total + 4095) / 4096));
+    const long long chunk = (total + nb1 - 1) / nb1;
+    hipLaunchKernelGGL(k_reduce1, dim3(nb1), dim3(kFinBlock), 0, s, partials, plan.items,
+                       plan.bf16 ? gc.count : nullptr, epart, (long long)plan.edge_blocks, chunk, red);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, s, red, nb1, loss, cnt, hits_out, status);
     return hipGetLastError();
 }
 
