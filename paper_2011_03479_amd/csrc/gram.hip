@@ -11,9 +11,9 @@
 //   covers the FP32 accumulation of G~ and of the norms), a pair whose computed
 //   delta~^2 = n~_i + n~_j - 2 G~ is >= theta_ij^2 has true delta >= mu + near_k sigma.
 //
-// The test uses one theta per 128 x 128 tile (the largest |x| of its rows and columns),
-// which only makes it stricter, and is evaluated as G~ - h_i > h_j with
-// h = n~/2 - theta^2/4, two VALU operations per pair.  Flagged sub-tiles are compacted in
+// The test uses one theta per pair of 128-vertex blocks (the largest |x| of each block),
+// which only makes it stricter, and is evaluated as G~ - n~_i/2 > n~_j/2 - theta^2/2,
+// two VALU operations per pair.  Flagged sub-tiles are compacted in
 // tile order and recomputed exactly in FP32 by the LDS sweep (k_sweep_wide over the
 // list); every other non-edge pair has delta >= mu + near_k sigma and is flushed: it
 // contributes less than -log2 Phi(-near_k) bits (< 2e-19 at near_k = 9) and a gradient
@@ -31,20 +31,6 @@ namespace gempe {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kXcdG = 8;
-
-__device__ inline void tile_of_g(long long t, int nt, int &I, int &J) {
-    double b = 2.0 * nt + 1.0;
-    long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
-    if (i < 0) i = 0;
-    if (i > nt - 1) i = nt - 1;
-    auto start = [nt](long long ii) { return ii * nt - ii * (ii - 1) / 2; };
-    while (i > 0 && start(i) > t) --i;
-    while (i + 1 < nt && start(i + 1) <= t) ++i;
-    I = (int)i;
-    J = (int)(i + (t - start(i)));
-}
-
 __device__ __forceinline__ long long upper_index(long long r, long long c, long long nt) {
     return r * nt - r * (r - 1) / 2 + (c - r);
 }
@@ -56,7 +42,9 @@ __device__ __forceinline__ float wave_sum_g(float v) {
 }
 
 // One wave per vertex: X~ = bf16(X) (round to nearest even), n~ = |x~|^2 (FP32 from the
-// rounded values), s = |x| (FP32, from the unrounded coordinates).
+// rounded values), s = |x| (FP32, from the unrounded coordinates).  A vertex with a
+// non-finite coordinate gets s = +inf: every tile it touches then counts as near, so the
+// exact pass sees (and reports) the non-finite value instead of the screen flushing it.
 __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ X, int n, int d,
                                                    __bf16 *__restrict__ Xb, float *__restrict__ nrm,
                                                    float *__restrict__ snorm) {
@@ -76,113 +64,171 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ X, 
     sx = wave_sum_g(sx);
     if (lane == 0) {
         nrm[v] = sb;
-        snorm[v] = sqrtf(sx);
+        snorm[v] = isfinite(sx) ? sqrtf(sx) : INFINITY;
     }
 }
 
-// Screen of one 128 x 128 tile (I, J), I <= J, four waves of 64 x 64.  Writes flags[t64]
-// (1: some pair of the 64 x 64 sub-tile may be near) for every sub-tile on or above the
-// diagonal, so the flag array needs no clearing between calls.
+// Largest |x| of every 128-vertex block (for the per-tile threshold of the screen).
+__global__ __launch_bounds__(128) void k_blockmax(const float *__restrict__ snorm, int n,
+                                                  float *__restrict__ smax128) {
+    __shared__ float w[2];
+    const int v = blockIdx.x * 128 + threadIdx.x;
+    float s = v < n ? snorm[v] : 0.0f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s = fmaxf(s, __shfl_xor(s, off, 64));
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) smax128[blockIdx.x] = fmaxf(w[0], w[1]);
+}
+
+// Screen of the 128-row strip I against 256-column tiles J = J0 + q, J0 + q + Q, ...
+// (item I*Q + q, J0 = I/2, the first tile reaching the diagonal).  The strip's operand
+// fragments and row terms are loaded once into registers; the column tiles stream through
+// two LDS buffers, the next tile's global loads issued before the current tile's MFMAs.
+// Eight waves, one 64 x 64 sub-tile each (rows 64 wr.., columns 64 wc.. of the tile): the
+// register budget then allows two waves per SIMD, so one wave's MFMAs cover the other's
+// LDS waits.  Writes flags[t64] (1: some pair of the 64 x 64 sub-tile may be near) for every
+// sub-tile on or above the diagonal, so the flags need no clearing between calls.
+constexpr int kScreenThreads = 512;
+
 template <int D>
-__global__ __launch_bounds__(256) void k_gram_screen(const __bf16 *__restrict__ Xb,
+__global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__restrict__ Xb,
                                                      const float *__restrict__ nrm,
-                                                     const float *__restrict__ snorm, int n, int nt128,
-                                                     long long items, long long per_xcd, long long nb64,
-                                                     float theta0, unsigned char *__restrict__ flags) {
-    constexpr int S = D + 8;  // padded LDS row stride (bf16): rows fall on different banks
-    __shared__ __attribute__((aligned(16))) __bf16 As[128 * S];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[128 * S];
-    __shared__ float hA[128], hB[128];
-    __shared__ float red[2][4];
+                                                     const float *__restrict__ smax128, int n, int nt128,
+                                                     int nt256, int Q, long long nb64, float theta0,
+                                                     unsigned char *__restrict__ flags) {
+    constexpr int S = D + 8;   // padded LDS row stride (bf16): rows fall on different banks
+    constexpr int CH = D / 8;  // 16-byte chunks per row
+    constexpr int TC = 256;    // columns per tile
+    constexpr int NT = kScreenThreads;
+    constexpr int PER = (TC * CH + NT - 1) / NT;  // chunks each thread stages per tile
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TC * S];
+    __shared__ float hA[128], hB[2][TC];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const long long t = (blockIdx.x % kXcdG) * per_xcd + blockIdx.x / kXcdG;
-    if (t >= items) return;
-    int I, J;
-    tile_of_g(t, nt128, I, J);
-    const int r0 = I * 128, c0 = J * 128;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: branches stay scalar
+    const int I = blockIdx.x / Q, q = blockIdx.x % Q;
+    int J = I / 2 + q;
+    if (J >= nt256) return;  // uniform over the workgroup
+    const int r0 = I * 128;
+    const float sI = smax128[I];
 
-    // stage the two 128-row slabs of X~ (16-byte chunks), zero beyond n
-    constexpr int CH = D / 8;  // 16-byte chunks per row
-    for (int q = tid; q < 128 * CH; q += 256) {
-        int row = q / CH, ch = q - row * CH;
-        bf16x8 va = {}, vb = {};
-        if (r0 + row < n) va = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(r0 + row) * D + ch * 8);
-        if (c0 + row < n) vb = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(c0 + row) * D + ch * 8);
-        *reinterpret_cast<bf16x8 *>(As + row * S + ch * 8) = va;
-        *reinterpret_cast<bf16x8 *>(Bs + row * S + ch * 8) = vb;
-    }
-    // theta of this tile from the largest |x| among its rows and among its columns
-    float sa = 0.0f, sb = 0.0f;
-    if (tid < 128) {
-        sa = (r0 + tid < n) ? snorm[r0 + tid] : 0.0f;
-    } else {
-        sb = (c0 + tid - 128 < n) ? snorm[c0 + tid - 128] : 0.0f;
-    }
+    auto stage = [&](int Jt, bf16x8 (&regs)[PER]) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sa = fmaxf(sa, __shfl_xor(sa, off, 64));
-        sb = fmaxf(sb, __shfl_xor(sb, off, 64));
-    }
-    if (lane == 0) red[0][wave] = sa, red[1][wave] = sb;
-    __syncthreads();
-    const float smaxA = fmaxf(red[0][0], red[0][1]);
-    const float smaxB = fmaxf(red[1][2], red[1][3]);
-    const float th = theta0 + 0.0078125f * (smaxA + smaxB);  // 2^-7
-    const float q4 = 0.25f * th * th;
-    if (tid < 128) {
-        hA[tid] = (r0 + tid < n) ? 0.5f * nrm[r0 + tid] - q4 : INFINITY;
-    } else {
-        hB[tid - 128] = (c0 + tid - 128 < n) ? 0.5f * nrm[c0 + tid - 128] - q4 : INFINITY;
-    }
-    __syncthreads();
+        for (int p = 0; p < PER; ++p) {
+            const int c = tid + p * NT;
+            const int row = c / CH, ch = c - row * CH;
+            bf16x8 v = {};
+            if (c < TC * CH && Jt * TC + row < n)
+                v = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(Jt * TC + row) * D + ch * 8);
+            regs[p] = v;
+        }
+    };
+    auto commit = [&](int Jt, int buf, const bf16x8 (&regs)[PER]) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int c = tid + p * NT;
+            const int row = c / CH, ch = c - row * CH;
+            if (c < TC * CH) *reinterpret_cast<bf16x8 *>(&Bs[buf][row * S + ch * 8]) = regs[p];
+        }
+        if (tid < TC) {
+            const int c = Jt * TC + tid;
+            // threshold of the 128 x 128 block pair: 2^-7 (|x_i| + |x_j|) margin
+            const float th = theta0 + 0.0078125f * (sI + smax128[min(c, n - 1) / 128]);
+            hB[buf][tid] = c < n ? 0.5f * nrm[c] - 0.5f * th * th : INFINITY;
+        }
+    };
 
-    const int wr = wave >> 1, wc = wave & 1;
-    const long long R64 = 2LL * I + wr, C64 = 2LL * J + wc;
-    if (R64 > C64 || C64 >= nb64) return;  // below the diagonal or past the last block
-
-    floatx16 acc[2][2];
+    // the strip's rows pass through buffer 1 into registers
+    for (int c = tid; c < 128 * CH; c += NT) {
+        const int row = c / CH, ch = c - row * CH;
+        bf16x8 v = {};
+        if (r0 + row < n) v = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(r0 + row) * D + ch * 8);
+        *reinterpret_cast<bf16x8 *>(&Bs[1][row * S + ch * 8]) = v;
+    }
+    if (tid < 128) hA[tid] = (r0 + tid < n) ? 0.5f * nrm[r0 + tid] : INFINITY;
+    __syncthreads();
+    const int wr = wave >> 2, wc = wave & 3;
+    const int lrow = lane & 31, lk = (lane >> 5) * 8;
+    bf16x8 afr[D / 16][2];
+#pragma unroll
+    for (int kk = 0; kk < D / 16; ++kk) {
+        afr[kk][0] = *reinterpret_cast<const bf16x8 *>(&Bs[1][(wr * 64 + lrow) * S + kk * 16 + lk]);
+        afr[kk][1] = *reinterpret_cast<const bf16x8 *>(&Bs[1][(wr * 64 + 32 + lrow) * S + kk * 16 + lk]);
+    }
+    float ha[2][16];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    const int lrow = lane & 31, lk = (lane >> 5) * 8;
-#pragma unroll
-    for (int kk = 0; kk < D; kk += 16) {
-        bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(As + (wr * 64 + lrow) * S + kk + lk);
-        bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(As + (wr * 64 + 32 + lrow) * S + kk + lk);
-        bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bs + (wc * 64 + lrow) * S + kk + lk);
-        bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bs + (wc * 64 + 32 + lrow) * S + kk + lk);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        for (int r = 0; r < 16; ++r) ha[a][r] = hA[wr * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)];
+    {
+        bf16x8 regs[PER];
+        stage(J, regs);
+        __syncthreads();  // buffer 1 is free again
+        commit(J, 0, regs);
     }
-    // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the 32 x 32 block
-    const bool diag = (R64 == C64);
-    bool near = false;
+    __syncthreads();
+
+    const long long R64 = 2LL * I + wr;
+    for (int it = 0; J < nt256; ++it, J += Q) {
+        const int cur = it & 1;
+        const int Jn = J + Q;
+        bf16x8 regs[PER];
+        if (Jn < nt256) stage(Jn, regs);
+
+        const long long C64 = 4LL * J + wc;  // this wave's sub-tile column
+        if (R64 <= C64 && C64 < nb64) {
+            floatx16 acc[2][2];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int jl = wc * 64 + b * 32 + (lane & 31);
-        const float hj = hB[jl];
-        const int jg = c0 + jl;
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int il = wr * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                bool hit = (acc[a][b][r] - hA[il]) > hj;
-                if (diag) hit = hit && (r0 + il < jg);
-                near = near || hit;
+                    for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+            const __bf16 *Bc = Bs[cur];
+#pragma unroll
+            for (int kk = 0; kk < D / 16; ++kk) {
+                bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + lrow) * S + kk * 16 + lk);
+                bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + 32 + lrow) * S + kk * 16 + lk);
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b1, acc[1][1], 0, 0, 0);
             }
+            // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block;
+            // near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>  delta~^2 < theta^2, taken on the
+            // largest G~ - n~_i/2 of the lane's column (one compare per column)
+            const bool diag = (R64 == C64);
+            bool near = false;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int jl = wc * 64 + b * 32 + (lane & 31);
+                float m = -INFINITY;
+                if (diag) {  // only pairs i < j of a diagonal sub-tile
+                    const int jg = J * TC + jl;
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int ig = r0 + wr * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                            m = fmaxf(m, ig < jg ? acc[a][b][r] - ha[a][r] : -INFINITY);
+                        }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r] - ha[a][r]);
+                }
+                near = near || (m > hB[cur][jl]);
+            }
+            const bool any = __ballot(near) != 0ull;
+            if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
         }
+        __syncthreads();  // every wave is done with buffer cur
+        if (Jn < nt256) commit(Jn, cur ^ 1, regs);
+        __syncthreads();
     }
-    const bool any = __ballot(near) != 0ull;
-    if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
 }
 
 // Ordered compaction of the flags: list[0..count) = indices of flagged 64 x 64 tiles in
@@ -240,27 +286,32 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(const unsigned char
 using namespace gempe;
 
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
-                                    float *snorm, unsigned char *flags, int *list, int *count, float theta0,
-                                    hipStream_t s) {
+                                    float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
+                                    float theta0, hipStream_t s) {
     const int n = g->n;
     hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d,
                        reinterpret_cast<__bf16 *>(Xb), nrm, snorm);
     const int nt128 = (n + 127) / 128;
-    const long long items = (long long)nt128 * (nt128 + 1) / 2;
-    const long long per = (items + kXcdG - 1) / kXcdG;
+    hipLaunchKernelGGL(k_blockmax, dim3((unsigned)nt128), dim3(128), 0, s, snorm, n, smax128);
     const long long nb64 = (n + 63) / 64;
+    const int nt256 = (n + 255) / 256;
+    // Q column tiles interleaved per strip: enough workgroups to fill the chip, strips
+    // long enough to amortise the resident rows
+    const int Q = std::max(1, std::min(8, nt256 / 2));
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(Xb);
-    dim3 grid((unsigned)(per * kXcdG)), block(256);
+    dim3 grid((unsigned)((long long)nt128 * Q)), block(kScreenThreads);
+#define GEMPE_SCREEN(DD) hipLaunchKernelGGL(k_gram_screen<DD>, grid, block, 0, s, xb, nrm, smax128, n, nt128, nt256, Q, nb64, theta0, flags)
     switch (d) {
-        case 16: hipLaunchKernelGGL(k_gram_screen<16>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 32: hipLaunchKernelGGL(k_gram_screen<32>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 48: hipLaunchKernelGGL(k_gram_screen<48>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 64: hipLaunchKernelGGL(k_gram_screen<64>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 80: hipLaunchKernelGGL(k_gram_screen<80>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 96: hipLaunchKernelGGL(k_gram_screen<96>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        case 112: hipLaunchKernelGGL(k_gram_screen<112>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
-        default: hipLaunchKernelGGL(k_gram_screen<128>, grid, block, 0, s, xb, nrm, snorm, n, nt128, items, per, nb64, theta0, flags); break;
+        case 16: GEMPE_SCREEN(16); break;
+        case 32: GEMPE_SCREEN(32); break;
+        case 48: GEMPE_SCREEN(48); break;
+        case 64: GEMPE_SCREEN(64); break;
+        case 80: GEMPE_SCREEN(80); break;
+        case 96: GEMPE_SCREEN(96); break;
+        case 112: GEMPE_SCREEN(112); break;
+        default: GEMPE_SCREEN(128); break;
     }
+#undef GEMPE_SCREEN
     const long long t64 = nb64 * (nb64 + 1) / 2;
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, s, flags, t64, list, count);
     return hipGetLastError();

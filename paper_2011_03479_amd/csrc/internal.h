@@ -113,6 +113,7 @@ struct WsLayout {
     size_t xb = 0;        // bf16[n*d] rounded coordinates
     size_t nrm = 0;       // float[n] squared norms of the rounded coordinates
     size_t snorm = 0;     // float[n] norms of the coordinates
+    size_t smax128 = 0;   // float[n/128] largest norm of every 128-vertex block
     size_t flags = 0;     // uint8[items] near flags of the 64x64 tiles
     size_t list = 0;      // int32[items] flagged tiles in order
     size_t total = 0;
@@ -130,7 +131,7 @@ PairParamsHost gempe_pair_params(const gempe_params *p);
 // Workspace pointers and threshold of the BF16 Gram screen (unused for FP32 plans).
 struct GramCtx {
     void *xb = nullptr;
-    float *nrm = nullptr, *snorm = nullptr;
+    float *nrm = nullptr, *snorm = nullptr, *smax128 = nullptr;
     unsigned char *flags = nullptr;
     int *list = nullptr, *count = nullptr;
     float theta0 = 0.0f;  // mu + near_k sigma
@@ -143,8 +144,8 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   const PairParamsHost &pp, hipStream_t s, bool clear_status,
                                   const GramCtx &gc, double *red);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
-                                    float *snorm, unsigned char *flags, int *list, int *count, float theta0,
-                                    hipStream_t s);
+                                    float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
+                                    float theta0, hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                          float *X, int iters, float eta, double *loss_hist,

@@ -275,9 +275,12 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 // LDS-resident sweep for wide embeddings (d in 17..128, and the exact pass of the BF16
 // screen), one wave per workgroup, tiles of 64 x 64.
 // ------------------------------------------------------------------------------------
-template <int D, bool ROWLOSS>
+// FLUSH (BF16 screen's exact pass only): a step whose 64 exact distances all satisfy
+// delta^2 >= far2 = (mu + near_k sigma)^2 skips the pair function and the gradient: those
+// pairs are far non-edges, flushed exactly as the screen flushes them.
+template <int D, bool ROWLOSS, bool FLUSH>
 __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int J, float *__restrict__ G,
-                           float *__restrict__ rowloss, const PairParams &P, float *lds) {
+                           float *__restrict__ rowloss, const PairParams &P, float *lds, float far2) {
     constexpr int S = D + 1;  // padded stride: lane-private rows hit distinct banks
     float *xr = lds;           // rows    [64][S]
     float *gr = xr + 64 * S;   // row gradients
@@ -307,6 +310,7 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
             float df = a[k] - b[k];
             r2 = __builtin_fmaf(df, df, r2);
         }
+        if (FLUSH && __ballot(!(r2 >= far2)) == 0ull) continue;  // wave-uniform: every pair far
         float dl, cc;
         pair_nonedge(r2, P, dl, cc);
         if (masked) {
@@ -314,6 +318,7 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
             dl = valid ? dl : 0.0f;
             cc = valid ? cc : 0.0f;
         }
+        if (FLUSH && r2 >= far2) dl = 0.0f, cc = 0.0f;
         loss += dl;
         if (ROWLOSS) lrow += dl;
         float *ga = gr + lane * S;
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
     if (t >= items) return;
     int I, J;
     tile_of(t, nt, I, J);
-    float l = wide_tile<D, ROWLOSS>(X, n, d, I, J, G, rowloss, P, lds);
+    float l = wide_tile<D, ROWLOSS, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
     if (threadIdx.x == 0) partials[t] = l;
 }
 
@@ -364,13 +369,13 @@ template <int D, bool ROWLOSS>
 __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict__ X, int n, int d, int nt,
                                                         const int *__restrict__ list, const int *__restrict__ count,
                                                         float *__restrict__ G, float *__restrict__ rowloss,
-                                                        float *__restrict__ partials, PairParams P) {
+                                                        float *__restrict__ partials, PairParams P, float far2) {
     extern __shared__ float lds[];
     const int cnt = *count;
     for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
         int I, J;
         tile_of(list[q], nt, I, J);
-        float l = wide_tile<D, ROWLOSS>(X, n, d, I, J, G, rowloss, P, lds);
+        float l = wide_tile<D, ROWLOSS, true>(X, n, d, I, J, G, rowloss, P, lds, far2);
         if (threadIdx.x == 0) partials[q] = l;
     }
 }
@@ -895,6 +900,8 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
         off = align256(off + sizeof(float) * (size_t)g->n);
         L.snorm = off;
         off = align256(off + sizeof(float) * (size_t)g->n);
+        L.smax128 = off;
+        off = align256(off + sizeof(float) * (size_t)((g->n + 127) / 128));
         L.flags = off;
         off = align256(off + (size_t)plan.items);
         L.list = off;
@@ -910,6 +917,7 @@ GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params 
     c.xb = ws + L.xb;
     c.nrm = reinterpret_cast<float *>(ws + L.nrm);
     c.snorm = reinterpret_cast<float *>(ws + L.snorm);
+    c.smax128 = reinterpret_cast<float *>(ws + L.smax128);
     c.flags = ws + L.flags;
     c.list = reinterpret_cast<int *>(ws + L.list);
     c.count = reinterpret_cast<int *>(ws + L.counters + 32);
@@ -975,7 +983,7 @@ void launch_wide_list(const SweepPlan &pl, hipStream_t s, const float *X, int n,
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sweep_wide_list<D, RL>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
-                       gc.list, gc.count, G, rl, part, P);
+                       gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0);
 }
 
 template <bool RL>
@@ -1032,8 +1040,8 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                            cnt, clear_status ? 2 : 1);
     }
     if (plan.bf16) {
-        hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.flags, gc.list, gc.count,
-                                                gc.theta0, s);
+        hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.smax128, gc.flags, gc.list,
+                                                gc.count, gc.theta0, s);
         if (e != hipSuccess) return e;
         if (row_loss)
             launch_list<true>(plan, s, X, n, d, gc, grad, row_loss, partials, P);
