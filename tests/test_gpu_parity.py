@@ -253,3 +253,23 @@ def test_pair_function_accuracy():
             gx = -d1 if dlt > 0 else 0.0
             assert abs(got["grad"][0, 0] - gx) <= rtol * abs(gx) + 1e-37, (edge, float(dlt), got["grad"][0, 0], gx)
             assert got["grad"][0, 1] == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_cl1m_sampled_rows(prec):
+    """The large all-pairs workload at full size (Chung-Lu n = 1,000,000, mean degree 20,
+    exponent 2.3, d = 16): sampled rows (including the hubs) against the oracle."""
+    from gpu_util import BF16_FLUSH_GRAD, BF16_GRAD_RTOL, BF16_LOSS_RTOL
+
+    w = synth.workload("cl1m" if prec == "fp32" else "cl1m_bf16")
+    g = w.graph
+    rng = np.random.default_rng(1)
+    hubs = np.argsort(-np.diff(g.row_ptr))[:6]
+    rows = np.unique(np.concatenate([rng.choice(g.n, 60, replace=False), hubs, [0, g.n - 1]]))
+    note(f"cl1m {prec} sampled rows, m={g.m}")
+    G = gempe.Graph(g.n, g.row_ptr, g.col_idx)
+    if prec == "fp32":
+        check_rows(g, G, w.X0, rows, what="cl1m fp32")
+    else:
+        check_rows(g, G, w.X0, rows, params=gempe.params_default(precision=1), what="cl1m bf16",
+                   loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL, grad_atol=(g.n - 1) * BF16_FLUSH_GRAD)
