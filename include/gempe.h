@@ -51,7 +51,7 @@ typedef enum gempe_status {
     GEMPE_ERR_HIP = -4,          /* a HIP runtime call failed                              */
     GEMPE_ERR_NUMERIC = -5,      /* non-finite loss or coordinates detected on the device  */
     GEMPE_ERR_UNSUPPORTED = -6,  /* valid request this build does not implement            */
-    GEMPE_ERR_TIMEOUT = -7       /* a device-side wait exceeded its bound                  */
+    GEMPE_ERR_TIMEOUT = -7       /* a wait exceeded its time limit (serving)               */
 } gempe_status;
 
 /* Arithmetic of the all-pairs sweep. */
@@ -145,10 +145,12 @@ gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta, double *l
  *   X         : float32[n*d], initial coordinates in, final coordinates out
  *   loss_hist : float64[iters+1] or NULL; loss_hist[k] = DL(X_k), k = 0..iters
  *               (computing loss_hist[iters] costs one extra loss-only sweep)
- * Runs as one persistent launch when the graph is small enough for one grid-wide
- * barrier per iteration to pay, else as a sequence of launches.  Synchronises the
- * stream once at the end to read the device status word: returns GEMPE_ERR_NUMERIC if
- * a non-finite loss appeared, GEMPE_ERR_TIMEOUT if a grid barrier wait ran out.
+ * For d <= 16 and at most 65,536 upper 64 x 64 tiles (n <= 23,000) every iteration is
+ * ONE fused launch (the previous step applied on the fly, the sweep, the edge pass and
+ * the FP64 loss of the previous iterate; the kernel boundary is the only global
+ * synchronisation); otherwise each iteration is a loss/gradient evaluation followed by
+ * the update.  Synchronises the stream once at the end to read the device status word:
+ * returns GEMPE_ERR_NUMERIC if a non-finite loss appeared during the run.
  */
 gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, float eta,
                          double *loss_hist, void *ws, size_t ws_bytes, const gempe_params *p,

@@ -29,7 +29,7 @@ extern "C" const char *gempe_status_string(gempe_status s) {
         case GEMPE_ERR_HIP: return "HIP runtime error";
         case GEMPE_ERR_NUMERIC: return "non-finite value";
         case GEMPE_ERR_UNSUPPORTED: return "unsupported";
-        case GEMPE_ERR_TIMEOUT: return "device wait timed out";
+        case GEMPE_ERR_TIMEOUT: return "wait timed out";
     }
     return "unknown status";
 }
@@ -147,8 +147,8 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     const long long nd = (long long)g->n * d;
     if (iters == 0 && !loss_hist) return GEMPE_OK;
     if (plan.persist) {
-        // one cooperative launch for the whole run
-        GEMPE_HIP_TRY(gempe_launch_embed_persistent(g, d, plan, X, iters, eta, loss_hist, L, w, pp, stream));
+        // one fused launch per iteration
+        GEMPE_HIP_TRY(gempe_launch_embed_fused(g, d, plan, X, iters, eta, loss_hist, L, w, pp, stream));
     } else {
         // the status word is cleared by the first sweep only, so it is sticky over the run
         for (int k = 0; k <= iters; ++k) {
@@ -164,6 +164,5 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
     GEMPE_HIP_TRY(hipStreamSynchronize(stream));
     if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed: non-finite loss");
-    if (host_status & kStatusTimeout) return gempe_fail(GEMPE_ERR_TIMEOUT, "embed: grid barrier timed out");
     return GEMPE_OK;
 }

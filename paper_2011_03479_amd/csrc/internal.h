@@ -12,7 +12,7 @@
 // Device-side status bits (gempe_graph_s::status_dev and the embed status word).
 enum : unsigned {
     kStatusNonFinite = 1u,    // a loss partial or a coordinate was NaN/Inf
-    kStatusTimeout = 2u,      // a grid-barrier wait ran out of its spin budget
+    kStatusReserved = 2u,     // unused
     kStatusBadRowPtr = 4u,    // row_ptr not monotone / out of [0, nnz]
     kStatusBadCol = 8u,       // column id out of range or a self-loop
     kStatusUnsorted = 16u,    // a row not strictly ascending (duplicate or unsorted)
@@ -107,7 +107,6 @@ struct WsLayout {
     size_t xbuf = 0;      // float[n*d] embed: second slot of the double-buffered iterate
     size_t gring = 0;     // float[3*n*d] embed: three gradient slots
     size_t ppart = 0;     // float[2*plan.units] embed: double-buffered loss partials
-    size_t barrier = 0;   // 256 B (reserved)
     size_t red = 0;       // double[1024] first level of the FP64 loss reduction
     // BF16 Gram screen
     size_t xb = 0;        // bf16[n*d] rounded coordinates
@@ -147,7 +146,7 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
-hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan,
+hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                          float *X, int iters, float eta, double *loss_hist,
                                          const WsLayout &L, unsigned char *ws,
                                          const PairParamsHost &pp, hipStream_t s);

@@ -81,7 +81,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // Coordinates of the current iterate: X[v], or X[v] - eta G[v] when a step of gradient
-// descent is applied on the fly (persistent loop).  Both the sweep and the edge pass read
+// descent is applied on the fly (fused iteration).  Both the sweep and the edge pass read
 // through this view, so they see bit-identical coordinates.
 struct XView {
     const float *X;
@@ -889,8 +889,6 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     off = align256(off + sizeof(float) * 3 * nd);
     L.ppart = off;
     off = align256(off + sizeof(float) * 2 * (size_t)std::max<long long>(plan.units, 1));
-    L.barrier = off;
-    off += 256;
     L.red = off;
     off = align256(off + sizeof(double) * kRed1Blocks);
     if (plan.bf16) {
@@ -1090,7 +1088,7 @@ hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long coun
     return hipGetLastError();
 }
 
-hipError_t gempe_launch_embed_persistent(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
+hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
                                          int iters, float eta, double *loss_hist, const WsLayout &L,
                                          unsigned char *ws, const PairParamsHost &pph, hipStream_t s) {
     const long long nd = (long long)g->n * d;
