@@ -156,6 +156,90 @@ gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, floa
                          double *loss_hist, void *ws, size_t ws_bytes, const gempe_params *p,
                          hipStream_t stream);
 
+/* ------------------------------------------------------------------------------------
+ * Serving: a request loop that runs many embedding jobs (each one gempe_embed-style
+ * gradient-descent run on its own graph) on one GPU with continuous batching.
+ *
+ * The server owns one device block of `budget_bytes`; every admitted job's graph,
+ * coordinates, loss history and workspace are carved from it (first fit), so the budget
+ * is a hard bound and admission never calls the device allocator.  A job is admitted, in
+ * order of arrival, as soon as its footprint fits; later jobs that fit may pass a job
+ * that does not, until that job has waited 2 s.  Jobs with d <= 16, FP32 and at most
+ * 65,536 upper 64 x 64 tiles advance together, one iteration per launch for all of them
+ * (a job arriving while others run joins at the next launch); other jobs run their
+ * iterations on separate streams, overlapping with those launches and with each other.
+ * Results (final coordinates, loss history) are copied to the caller's host buffers when
+ * a job finishes.  A job's result equals what gempe_embed computes for it alone, up to
+ * the order of FP32 atomic additions in the gradient.  A job whose loss becomes
+ * non-finite, or whose graph is invalid, fails alone.
+ * ------------------------------------------------------------------------------------ */
+typedef struct gempe_server_s *gempe_server;
+
+enum { GEMPE_JOB_QUEUED = 0, GEMPE_JOB_RUNNING = 1, GEMPE_JOB_DONE = 2, GEMPE_JOB_FAILED = 3 };
+
+typedef struct gempe_job_desc {
+    int32_t n;               /* vertices, >= 2                                               */
+    int32_t d;               /* embedding dimension, 1..128                                  */
+    int64_t nnz;             /* CSR entries, 2m                                              */
+    const int64_t *row_ptr;  /* [host] int64[n+1], rules of gempe_graph_create               */
+    const int32_t *col_idx;  /* [host] int32[nnz]                                            */
+    const float *X0;         /* [host] float32[n*d] initial coordinates                      */
+    int32_t iters;           /* gradient-descent steps, >= 0                                 */
+    float eta;               /* step size, finite and > 0                                    */
+    gempe_params params;     /* as for gempe_embed                                           */
+    double release_s;        /* arrival time in seconds after server creation; the job is
+                                not admitted before it (earlier values mean "now")          */
+    float *X_out;            /* [host] float32[n*d], final coordinates, written at DONE      */
+    double *loss_hist;       /* [host] float64[iters+1] or NULL, DL(X_k), written at DONE    */
+} gempe_job_desc;
+
+typedef struct gempe_job_info {
+    int32_t state;      /* GEMPE_JOB_*                                                       */
+    int32_t status;     /* gempe_status of a failed job, GEMPE_OK otherwise                  */
+    int32_t batched;    /* 1 if the job ran in the shared per-iteration launches             */
+    int32_t reserved;
+    double release_s;   /* arrival, admission and completion times, seconds after creation */
+    double admit_s;
+    double done_s;
+    uint64_t footprint; /* bytes of the budget the job held while running                   */
+} gempe_job_info;
+
+typedef struct gempe_server_stats {
+    int64_t submitted, admitted, done, failed, rejected;
+    int64_t ticks;           /* shared per-iteration launches issued                         */
+    int64_t peak_bytes;      /* high-water mark of the budget in use                         */
+    int64_t max_concurrent;  /* most jobs on the device at once                              */
+    int64_t budget_bytes;
+    double pairs;            /* unordered vertex pairs x iterations of the finished jobs     */
+} gempe_server_stats;
+
+/* Bytes of the budget a job of this shape holds while it runs (0 on invalid arguments). */
+size_t gempe_job_footprint(int32_t n, int64_t nnz, int32_t d, int32_t iters, const gempe_params *p);
+
+/* Creates a server on the current device with a budget of budget_bytes (>= 4 KiB,
+ * allocated at once: GEMPE_ERR_NOMEM if that fails) and at most max_jobs (1..4096) jobs
+ * on the device at once.  Starts the scheduler thread. [host] */
+gempe_status gempe_server_create(size_t budget_bytes, int32_t max_jobs, gempe_server *out);
+
+/* Queues a job; copies the request's host arrays (they may be freed on return); X_out
+ * and loss_hist must stay valid until the job is DONE or FAILED.  GEMPE_ERR_NOMEM (the
+ * job is rejected) if its footprint exceeds the whole budget; argument errors as for
+ * gempe_graph_create / gempe_embed; an invalid graph fails the job at admission. [host] */
+gempe_status gempe_server_submit(gempe_server s, const gempe_job_desc *job, int64_t *job_id);
+
+/* State of a job (GEMPE_ERR_ARG for an unknown id). [host] */
+gempe_status gempe_server_query(gempe_server s, int64_t job_id, gempe_job_info *info);
+
+/* Waits until the job is DONE or FAILED (job_id < 0: until every submitted job is), at
+ * most timeout_s seconds (< 0: no limit); GEMPE_ERR_TIMEOUT when the limit passes. [host] */
+gempe_status gempe_server_wait(gempe_server s, int64_t job_id, double timeout_s, gempe_job_info *info);
+
+gempe_status gempe_server_get_stats(gempe_server s, gempe_server_stats *out); /* [host] */
+
+/* Stops the scheduler, lets enqueued device work finish, marks unfinished jobs FAILED and
+ * frees the server's memory. [host] */
+gempe_status gempe_server_destroy(gempe_server s);
+
 /* Static description of a status code. [host] */
 const char *gempe_status_string(gempe_status s);
 

@@ -44,13 +44,10 @@ extern "C" void gempe_params_default(gempe_params *p) {
     p->flags = GEMPE_F_NONE;
 }
 
-namespace {
-
-gempe_status check_common(gempe_graph g, int32_t d, const gempe_params *p, const char *who) {
+gempe_status gempe_check_problem(int32_t n, int32_t d, const gempe_params *p, const char *who) {
     std::string w(who);
-    if (!g) return gempe_fail(GEMPE_ERR_ARG, w + ": null graph handle");
     if (!p) return gempe_fail(GEMPE_ERR_ARG, w + ": null params");
-    if (g->n < 2) return gempe_fail(GEMPE_ERR_ARG, w + ": the graph needs n >= 2 vertices");
+    if (n < 2) return gempe_fail(GEMPE_ERR_ARG, w + ": the graph needs n >= 2 vertices");
     if (d < 1 || d > 128) return gempe_fail(GEMPE_ERR_ARG, w + ": d must be in [1, 128]");
     if (!(std::isfinite(p->mu) && std::isfinite(p->sigma) && p->sigma > 0.0))
         return gempe_fail(GEMPE_ERR_ARG, w + ": mu must be finite and sigma finite and > 0");
@@ -65,6 +62,13 @@ gempe_status check_common(gempe_graph g, int32_t d, const gempe_params *p, const
     if (p->precision != GEMPE_FP32 && p->precision != GEMPE_BF16_GRAM)
         return gempe_fail(GEMPE_ERR_ARG, w + ": unknown precision");
     return GEMPE_OK;
+}
+
+namespace {
+
+gempe_status check_common(gempe_graph g, int32_t d, const gempe_params *p, const char *who) {
+    if (!g) return gempe_fail(GEMPE_ERR_ARG, std::string(who) + ": null graph handle");
+    return gempe_check_problem(g->n, d, p, who);
 }
 
 gempe_status check_ws(gempe_graph g, int32_t d, const void *ws, size_t ws_bytes, const WsLayout &L,
@@ -126,6 +130,28 @@ extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta
     return GEMPE_OK;
 }
 
+hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepPlan &plan, const WsLayout &L,
+                                     unsigned char *w, float *X, int iters, float eta, double *loss_hist,
+                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end) {
+    float *G = reinterpret_cast<float *>(w + L.gbuf);
+    float *part = reinterpret_cast<float *>(w + L.partials);
+    double *scratch_loss = reinterpret_cast<double *>(w + L.counters + 16);
+    const PairParamsHost pp = gempe_pair_params(p);
+    const GramCtx gc = gempe_gram_ctx(L, w, p);
+    const long long nd = (long long)g->n * d;
+    // the status word is cleared by the first sweep only, so it is sticky over the run
+    for (int k = k_begin; k < k_end && k <= iters; ++k) {
+        const bool last = (k == iters);
+        if (last && !loss_hist) break;
+        double *lossp = loss_hist ? loss_hist + k : scratch_loss;
+        hipError_t e = gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr, pp,
+                                              stream, k == 0, gc, reinterpret_cast<double *>(w + L.red));
+        if (e != hipSuccess) return e;
+        if (!last && (e = gempe_launch_axpy(X, G, eta, nd, stream)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, float eta,
                                     double *loss_hist, void *ws, size_t ws_bytes, const gempe_params *p,
                                     hipStream_t stream) {
@@ -138,27 +164,14 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
     WsLayout L = gempe_ws_layout(g, d, plan);
     if ((st = check_ws(g, d, ws, ws_bytes, L, "embed")) != GEMPE_OK) return st;
     unsigned char *w = static_cast<unsigned char *>(ws);
-    float *G = reinterpret_cast<float *>(w + L.gbuf);
-    float *part = reinterpret_cast<float *>(w + L.partials);
     unsigned *status_ws = reinterpret_cast<unsigned *>(w + L.counters + 8);
-    double *scratch_loss = reinterpret_cast<double *>(w + L.counters + 16);
-    PairParamsHost pp = gempe_pair_params(p);
-    const GramCtx gc = gempe_gram_ctx(L, w, p);
-    const long long nd = (long long)g->n * d;
+    const PairParamsHost pp = gempe_pair_params(p);
     if (iters == 0 && !loss_hist) return GEMPE_OK;
     if (plan.persist) {
         // one fused launch per iteration
         GEMPE_HIP_TRY(gempe_launch_embed_fused(g, d, plan, X, iters, eta, loss_hist, L, w, pp, stream));
     } else {
-        // the status word is cleared by the first sweep only, so it is sticky over the run
-        for (int k = 0; k <= iters; ++k) {
-            bool last = (k == iters);
-            if (last && !loss_hist) break;
-            double *lossp = loss_hist ? loss_hist + k : scratch_loss;
-            GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr,
-                                                 pp, stream, k == 0, gc, reinterpret_cast<double *>(w + L.red)));
-            if (!last) GEMPE_HIP_TRY(gempe_launch_axpy(X, G, eta, nd, stream));
-        }
+        GEMPE_HIP_TRY(gempe_enqueue_embed_steps(g, d, plan, L, w, X, iters, eta, loss_hist, p, stream, 0, iters + 1));
     }
     unsigned host_status = 0;
     GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));

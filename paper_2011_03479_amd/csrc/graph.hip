@@ -113,70 +113,83 @@ unsigned blocks_for(int64_t count) {
     return (unsigned)std::max<int64_t>(1, (count + kBlock - 1) / kBlock);
 }
 
-void free_graph(gempe_graph_s *g) {
-    if (!g) return;
-    if (g->row_ptr) (void)hipFree(g->row_ptr);
-    if (g->col_idx) (void)hipFree(g->col_idx);
-    if (g->coo_row) (void)hipFree(g->coo_row);
-    if (g->hash) (void)hipFree(g->hash);
-    if (g->status_dev) (void)hipFree(g->status_dev);
-    delete g;
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct GraphOffsets {
+    size_t row_ptr, col_idx, coo_row, hash, status, total;
+};
+
+GraphOffsets graph_offsets(int32_t n, int64_t nnz, uint64_t cap) {
+    GraphOffsets o;
+    size_t off = 0;
+    o.status = off;
+    off += 256;
+    o.row_ptr = off;
+    off = align256(off + sizeof(int64_t) * ((size_t)n + 1));
+    o.col_idx = off;
+    off = align256(off + sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    o.coo_row = off;
+    off = align256(off + sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    o.hash = off;
+    off = align256(off + sizeof(unsigned long long) * cap);
+    o.total = off;
+    return o;
+}
+
+uint64_t hash_capacity(int64_t m) {
+    uint64_t cap = 2;
+    while (cap < 2 * (uint64_t)m) cap <<= 1;
+    return cap;
 }
 
 }  // namespace
 
-extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t *row_ptr,
-                                           const int32_t *col_idx, hipStream_t stream,
-                                           gempe_graph *out) {
-    if (!out) return gempe_fail(GEMPE_ERR_ARG, "graph_create: out is NULL");
-    *out = nullptr;
-    if (n < 1) return gempe_fail(GEMPE_ERR_ARG, "graph_create: n must be >= 1");
-    if (nnz < 0 || (nnz & 1)) return gempe_fail(GEMPE_ERR_GRAPH, "graph_create: nnz must be even and >= 0");
+gempe_status gempe_graph_check_args(int32_t n, int64_t nnz, const void *row_ptr, const void *col_idx,
+                                    const char *who) {
+    const std::string w(who);
+    if (n < 1) return gempe_fail(GEMPE_ERR_ARG, w + ": n must be >= 1");
+    if (nnz < 0 || (nnz & 1)) return gempe_fail(GEMPE_ERR_GRAPH, w + ": nnz must be even and >= 0");
     if ((uint64_t)nnz > (uint64_t)n * (uint64_t)(n - 1))
-        return gempe_fail(GEMPE_ERR_GRAPH, "graph_create: nnz exceeds n(n-1)");
-    if (!row_ptr || (nnz > 0 && !col_idx)) return gempe_fail(GEMPE_ERR_ARG, "graph_create: null CSR pointer");
+        return gempe_fail(GEMPE_ERR_GRAPH, w + ": nnz exceeds n(n-1)");
+    if (!row_ptr || (nnz > 0 && !col_idx)) return gempe_fail(GEMPE_ERR_ARG, w + ": null CSR pointer");
+    return GEMPE_OK;
+}
 
-    gempe_graph_s *g = new gempe_graph_s();
+size_t gempe_graph_mem_bytes(int32_t n, int64_t nnz) {
+    return graph_offsets(n, nnz, hash_capacity(nnz / 2)).total;
+}
+
+gempe_status gempe_graph_build(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                               hipMemcpyKind kind, void *mem, hipStream_t stream, gempe_graph_s *g) {
     g->n = n;
     g->nnz = nnz;
     g->m = nnz / 2;
     GEMPE_HIP_TRY(hipGetDevice(&g->device));
-    uint64_t cap = 2;
-    while (cap < 2 * (uint64_t)g->m) cap <<= 1;
+    const uint64_t cap = hash_capacity(g->m);
     g->hash_cap = cap;
+    const GraphOffsets o = graph_offsets(n, nnz, cap);
+    unsigned char *base = static_cast<unsigned char *>(mem);
+    g->mem = mem;
+    g->status_dev = reinterpret_cast<unsigned *>(base + o.status);
+    g->row_ptr = reinterpret_cast<int64_t *>(base + o.row_ptr);
+    g->col_idx = reinterpret_cast<int32_t *>(base + o.col_idx);
+    g->coo_row = reinterpret_cast<int32_t *>(base + o.coo_row);
+    g->hash = reinterpret_cast<unsigned long long *>(base + o.hash);
 
-#define GRAPH_TRY(expr)                                                                  \
-    do {                                                                                 \
-        hipError_t _e = (expr);                                                          \
-        if (_e != hipSuccess) {                                                          \
-            free_graph(g);                                                               \
-            return gempe_fail(GEMPE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
-        }                                                                                \
-    } while (0)
-
-    GRAPH_TRY(hipMalloc(&g->row_ptr, sizeof(int64_t) * (n + 1)));
-    GRAPH_TRY(hipMalloc(&g->col_idx, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-    GRAPH_TRY(hipMalloc(&g->coo_row, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
-    GRAPH_TRY(hipMalloc(&g->hash, sizeof(unsigned long long) * cap));
-    GRAPH_TRY(hipMalloc(&g->status_dev, 256));
-    GRAPH_TRY(hipMemsetAsync(g->status_dev, 0, 256, stream));
-    GRAPH_TRY(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, stream));
-    if (nnz > 0)
-        GRAPH_TRY(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, stream));
+    GEMPE_HIP_TRY(hipMemsetAsync(g->status_dev, 0, 256, stream));
+    GEMPE_HIP_TRY(hipMemcpyAsync(g->row_ptr, row_ptr, sizeof(int64_t) * (n + 1), kind, stream));
+    if (nnz > 0) GEMPE_HIP_TRY(hipMemcpyAsync(g->col_idx, col_idx, sizeof(int32_t) * nnz, kind, stream));
     unsigned *status = g->status_dev;
     unsigned long long *upper = reinterpret_cast<unsigned long long *>(g->status_dev + 2);
     unsigned long long *lower = reinterpret_cast<unsigned long long *>(g->status_dev + 4);
 
     // 1. row_ptr shape; everything after indexes through it, so stop here if it is bad.
     k_check_row_ptr<<<blocks_for(n + 1), kBlock, 0, stream>>>(g->row_ptr, n, nnz, status);
-    GRAPH_TRY(hipGetLastError());
+    GEMPE_HIP_TRY(hipGetLastError());
     unsigned host_status = 0;
-    GRAPH_TRY(hipMemcpyAsync(&host_status, status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
-    GRAPH_TRY(hipStreamSynchronize(stream));
-    if (host_status) {
-        free_graph(g);
-        return gempe_fail(GEMPE_ERR_GRAPH, "graph_create: row_ptr is not a valid CSR offset array");
-    }
+    GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+    if (host_status) return gempe_fail(GEMPE_ERR_GRAPH, "graph_create: row_ptr is not a valid CSR offset array");
     // 2. entry checks, hash insertion of the i<j half, mirror lookups of the i>j half.
     k_fill_u64<<<blocks_for((int64_t)cap), kBlock, 0, stream>>>(g->hash, kHashEmpty, cap);
     if (nnz > 0) {
@@ -186,11 +199,10 @@ extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t
         k_check_mirror<<<blocks_for(nnz), kBlock, 0, stream>>>(g->col_idx, g->coo_row, nnz, g->hash, cap,
                                                                 status, lower);
     }
-    GRAPH_TRY(hipGetLastError());
+    GEMPE_HIP_TRY(hipGetLastError());
     unsigned host_words[6] = {0, 0, 0, 0, 0, 0};
-    GRAPH_TRY(hipMemcpyAsync(host_words, status, sizeof(host_words), hipMemcpyDeviceToHost, stream));
-    GRAPH_TRY(hipStreamSynchronize(stream));
-#undef GRAPH_TRY
+    GEMPE_HIP_TRY(hipMemcpyAsync(host_words, status, sizeof(host_words), hipMemcpyDeviceToHost, stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
     unsigned long long nup, nlo;
     std::memcpy(&nup, host_words + 2, 8);
     std::memcpy(&nlo, host_words + 4, 8);
@@ -202,8 +214,32 @@ extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t
         if (bits & kStatusAsymmetric) why += " (i,j) without (j,i);";
         if (bits & kStatusHashFull) why += " edge hash full;";
         if (!bits) why += " directed entry counts i<j and i>j differ;";
-        free_graph(g);
         return gempe_fail(GEMPE_ERR_GRAPH, "graph_create:" + why);
+    }
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                           const int32_t *col_idx, hipStream_t stream,
+                                           gempe_graph *out) {
+    if (!out) return gempe_fail(GEMPE_ERR_ARG, "graph_create: out is NULL");
+    *out = nullptr;
+    gempe_status st = gempe_graph_check_args(n, nnz, row_ptr, col_idx, "graph_create");
+    if (st != GEMPE_OK) return st;
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, gempe_graph_mem_bytes(n, nnz));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return gempe_fail(GEMPE_ERR_NOMEM, std::string("graph_create: hipMalloc: ") + hipGetErrorString(e));
+    }
+    gempe_graph_s *g = new gempe_graph_s();
+    g->owns_mem = true;
+    st = gempe_graph_build(n, nnz, row_ptr, col_idx, hipMemcpyDeviceToDevice, mem, stream, g);
+    if (st != GEMPE_OK) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(mem);
+        delete g;
+        return st;
     }
     *out = g;
     return GEMPE_OK;
@@ -211,8 +247,10 @@ extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t
 
 extern "C" gempe_status gempe_graph_destroy(gempe_graph g) {
     if (!g) return gempe_fail(GEMPE_ERR_ARG, "graph_destroy: null handle");
+    if (!g->owns_mem) return gempe_fail(GEMPE_ERR_ARG, "graph_destroy: handle is owned by a server");
     GEMPE_HIP_TRY(hipDeviceSynchronize());
-    free_graph(g);
+    (void)hipFree(g->mem);
+    delete g;
     return GEMPE_OK;
 }
 

@@ -31,10 +31,25 @@ struct gempe_graph_s {
     unsigned long long *hash = nullptr;  // device, open addressing, capacity hash_cap
     uint64_t hash_cap = 0;       // power of two >= 2m (>= 2)
     unsigned *status_dev = nullptr;  // device words: [0] graph validation, [1] counters
+    void *mem = nullptr;         // the one device block holding all of the above
+    bool owns_mem = false;       // allocated by gempe_graph_create (else by a server's arena)
 };
+
+// Host-side size checks shared by gempe_graph_create and the server's submit.
+gempe_status gempe_graph_check_args(int32_t n, int64_t nnz, const void *row_ptr, const void *col_idx,
+                                    const char *who);
+// Bytes of the device block of a graph (CSR copy, row ids, hash, status words).
+size_t gempe_graph_mem_bytes(int32_t n, int64_t nnz);
+// Copies (kind: device or host source) and validates a CSR into `mem` (gempe_graph_mem_bytes
+// bytes, 256-B aligned) and fills *g.  Synchronises `stream`.
+gempe_status gempe_graph_build(int32_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                               hipMemcpyKind kind, void *mem, hipStream_t stream, gempe_graph_s *g);
 
 // Empty slot marker of the edge hash (keys are (min << 32) | max with min < max < 2^31).
 constexpr unsigned long long kHashEmpty = ~0ull;
+
+// Host-side checks of (n, d, params) shared by every call (api.hip).
+gempe_status gempe_check_problem(int32_t n, int32_t d, const gempe_params *p, const char *who);
 
 // Thread-local error text (api.hip).
 void gempe_set_error(const std::string &msg);
@@ -146,7 +161,23 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
+// Continuous batching of fused iterations (sweep.hip): one table row per job.
+size_t gempe_batch_entry_bytes();
+void gempe_batch_entry_fill(void *dst, const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
+                            int iters, float eta, double *loss_hist, const WsLayout &L, unsigned char *ws,
+                            const PairParamsHost &pp, long long u0, int k0);
+hipError_t gempe_batch_prepare(const gempe_graph_s *g, int d, const WsLayout &L, unsigned char *ws,
+                               hipStream_t s);
+hipError_t gempe_launch_iter_batch(int D, const void *table, int njobs, long long blocks, int tick,
+                                   hipStream_t s);
 hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPlan &plan,
                                          float *X, int iters, float eta, double *loss_hist,
                                          const WsLayout &L, unsigned char *ws,
                                          const PairParamsHost &pp, hipStream_t s);
+
+// Enqueues iterations [k_begin, k_end) of a run that is not fused (an evaluation of the loss
+// and gradient followed by the step; k = iters is the final loss-only evaluation when
+// loss_hist is given).  k = 0 clears the status word.  Nothing is synchronised (api.hip).
+hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepPlan &plan, const WsLayout &L,
+                                     unsigned char *w, float *X, int iters, float eta, double *loss_hist,
+                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end);

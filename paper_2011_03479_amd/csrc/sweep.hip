@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "internal.h"
 #include "pairfn.h"
@@ -657,17 +658,26 @@ __device__ inline void reduce_loss(const IterArgs &a, int k, double *sh) {
     }
 }
 
+// LDS of one fused-iteration workgroup.
 template <int D>
-__global__ __launch_bounds__(256) void k_iter(IterArgs a, int k) {
-    __shared__ double sh[kFinBlock];
-    __shared__ float rowp[4][64 * D];  // per-wave partials: plain LDS stores, summed in wave order
-    __shared__ float colp[4][64 * D];
-    __shared__ float wl[4];
+struct IterLds {
+    double sh[kFinBlock];
+    float rowp[4][64 * D];  // per-wave partials: plain LDS stores, summed in wave order
+    float colp[4][64 * D];
+    float wl[4];
+};
+
+// Iteration k of one gradient-descent run, executed by workgroup b of the run's
+// `nthreads / 256` workgroups (gtid: this thread's index among them).
+template <int D>
+__device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long long gtid, long long nthreads,
+                                          IterLds<D> &L) {
+    double *sh = L.sh;
+    auto &rowp = L.rowp;
+    auto &colp = L.colp;
+    float *wl = L.wl;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int b = (int)blockIdx.x;
-    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nthreads = (long long)gridDim.x * blockDim.x;
     const long long nd = (long long)a.n * a.d;
     float *Xs[2] = {a.Xc, a.Xw};
     const float *Xprev = (k == 0) ? a.Xc : Xs[(k - 1) & 1];
@@ -762,14 +772,19 @@ __global__ __launch_bounds__(256) void k_iter(IterArgs a, int k) {
     if (threadIdx.x == 0) Pk[b] = (wl[0] + wl[1]) + (wl[2] + wl[3]);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_iter(IterArgs a, int k) {
+    __shared__ IterLds<D> lds;
+    iter_body<D>(a, k, (int)blockIdx.x, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                 (long long)gridDim.x * blockDim.x, lds);
+}
+
 // After K sweeps: the FP64 loss of the last sweep, and the final coordinates into the
 // caller's buffer (the last step applied now when no loss of the final iterate was asked).
-__global__ __launch_bounds__(256) void k_iter_finish(IterArgs a, int K, int iters) {
-    __shared__ double sh[kFinBlock];
-    const long long gtid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long nthreads = (long long)gridDim.x * blockDim.x;
+__device__ __forceinline__ void finish_body(const IterArgs &a, int K, int iters, int b, long long gtid,
+                                            long long nthreads, double *sh) {
     const long long nd = (long long)a.n * a.d;
-    if (blockIdx.x == 0 && K > 0 && a.loss_hist) reduce_loss(a, K - 1, sh);
+    if (b == 0 && K > 0 && a.loss_hist) reduce_loss(a, K - 1, sh);
     if (iters <= 0) return;
     if (K == iters + 1) {  // x_iters was written to slot iters&1 by the last sweep
         if (iters & 1)
@@ -779,6 +794,52 @@ __global__ __launch_bounds__(256) void k_iter_finish(IterArgs a, int K, int iter
         const float *Gl = a.G0 + (size_t)((iters - 1) % 3) * nd;
         for (long long v = gtid; v < nd; v += nthreads) a.Xc[v] = __builtin_fmaf(a.neg_eta, Gl[v], Xl[v]);
     }
+}
+
+__global__ __launch_bounds__(256) void k_iter_finish(IterArgs a, int K, int iters) {
+    __shared__ double sh[kFinBlock];
+    finish_body(a, K, iters, (int)blockIdx.x, (long long)blockIdx.x * blockDim.x + threadIdx.x,
+                (long long)gridDim.x * blockDim.x, sh);
+}
+
+// ------------------------------------------------------------------------------------
+// Continuous batching: many independent gradient-descent runs (jobs) advance by one
+// iteration per launch ("tick").  Job q owns workgroups [u0, u0 + blocks) of the tick;
+// its iteration index is k = tick - k0.  For k < K the workgroups run iteration k exactly
+// as k_iter does for a single run (same per-tile partials and reduction order); at k = K
+// they run the finishing step (loss of the last sweep, final coordinates).  Jobs share
+// nothing but the launch, so a job's result does not depend on its companions.
+// ------------------------------------------------------------------------------------
+struct BatchEntry {
+    IterArgs a;
+    long long u0;      // first workgroup of this job in the tick
+    long long blocks;  // workgroups of this job (its units)
+    int k0;            // tick of the job's iteration 0
+    int K;             // sweeps (iters, +1 when the loss of the final iterate is kept)
+    int iters;
+    int pad;
+};
+
+template <int D>
+__global__ __launch_bounds__(256) void k_iter_batch(const BatchEntry *__restrict__ tab, int njobs, int tick) {
+    __shared__ IterLds<D> lds;
+    const long long b = blockIdx.x;
+    // the job whose workgroup range holds b (entries ordered by u0)
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].u0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const BatchEntry &e = tab[lo];
+    const long long lb = b - e.u0;
+    if (lb >= e.blocks) return;  // uniform over the workgroup (cannot happen for a dense table)
+    const int k = tick - e.k0;
+    const long long gtid = lb * blockDim.x + threadIdx.x;
+    const long long nthreads = e.blocks * blockDim.x;
+    if (k >= 0 && k < e.K)
+        iter_body<D>(e.a, k, (int)lb, gtid, nthreads, lds);
+    else if (k == e.K)
+        finish_body(e.a, e.K, e.iters, (int)lb, gtid, nthreads, lds.sh);
 }
 
 }  // namespace gempe
@@ -1088,10 +1149,9 @@ hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long coun
     return hipGetLastError();
 }
 
-hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
-                                         int iters, float eta, double *loss_hist, const WsLayout &L,
-                                         unsigned char *ws, const PairParamsHost &pph, hipStream_t s) {
-    const long long nd = (long long)g->n * d;
+namespace {
+IterArgs make_iter_args(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X, float eta,
+                        double *loss_hist, const WsLayout &L, unsigned char *ws, const PairParamsHost &pph) {
     IterArgs a;
     a.Xc = X;
     a.Xw = reinterpret_cast<float *>(ws + L.xbuf);
@@ -1110,6 +1170,56 @@ hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPl
     a.units = plan.units;
     a.neg_eta = -eta;
     a.P = PairParams{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
+    return a;
+}
+}  // namespace
+
+size_t gempe_batch_entry_bytes() { return sizeof(BatchEntry); }
+
+void gempe_batch_entry_fill(void *dst, const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
+                            int iters, float eta, double *loss_hist, const WsLayout &L, unsigned char *ws,
+                            const PairParamsHost &pph, long long u0, int k0) {
+    BatchEntry e{};
+    e.a = make_iter_args(g, d, plan, X, eta, loss_hist, L, ws, pph);
+    e.u0 = u0;
+    e.blocks = std::max<long long>(1, plan.units);
+    e.k0 = k0;
+    e.K = iters + (loss_hist ? 1 : 0);
+    e.iters = iters;
+    std::memcpy(dst, &e, sizeof(e));
+}
+
+hipError_t gempe_batch_prepare(const gempe_graph_s *g, int d, const WsLayout &L, unsigned char *ws,
+                               hipStream_t s) {
+    // gradient slot 0 and the status word start at zero (a fill kernel, no memset)
+    const long long nd = (long long)g->n * d;
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(ws + L.counters);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256))),
+                       dim3(256), 0, s, reinterpret_cast<float *>(ws + L.gring), nd, nullptr, 0LL, cnt, 2);
+    return hipGetLastError();
+}
+
+hipError_t gempe_launch_iter_batch(int D, const void *table, int njobs, long long blocks, int tick,
+                                   hipStream_t s) {
+    const BatchEntry *t = static_cast<const BatchEntry *>(table);
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (D) {
+        case 1: hipLaunchKernelGGL(k_iter_batch<1>, grid, block, 0, s, t, njobs, tick); break;
+        case 2: hipLaunchKernelGGL(k_iter_batch<2>, grid, block, 0, s, t, njobs, tick); break;
+        case 3: hipLaunchKernelGGL(k_iter_batch<3>, grid, block, 0, s, t, njobs, tick); break;
+        case 4: hipLaunchKernelGGL(k_iter_batch<4>, grid, block, 0, s, t, njobs, tick); break;
+        case 8: hipLaunchKernelGGL(k_iter_batch<8>, grid, block, 0, s, t, njobs, tick); break;
+        case 16: hipLaunchKernelGGL(k_iter_batch<16>, grid, block, 0, s, t, njobs, tick); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
+                                    int iters, float eta, double *loss_hist, const WsLayout &L,
+                                    unsigned char *ws, const PairParamsHost &pph, hipStream_t s) {
+    const long long nd = (long long)g->n * d;
+    IterArgs a = make_iter_args(g, d, plan, X, eta, loss_hist, L, ws, pph);
     const int K = iters + (loss_hist ? 1 : 0);
     // clear gradient slot 0 and the status word (a fill kernel, no memset)
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(ws + L.counters);

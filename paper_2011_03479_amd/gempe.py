@@ -42,7 +42,19 @@ ABI_SYMBOLS = (
     "gempe_embed",
     "gempe_status_string",
     "gempe_last_error",
+    "gempe_job_footprint",
+    "gempe_server_create",
+    "gempe_server_submit",
+    "gempe_server_query",
+    "gempe_server_wait",
+    "gempe_server_get_stats",
+    "gempe_server_destroy",
 )
+
+GEMPE_JOB_QUEUED = 0
+GEMPE_JOB_RUNNING = 1
+GEMPE_JOB_DONE = 2
+GEMPE_JOB_FAILED = 3
 
 
 class GempeLibraryMissing(RuntimeError):
@@ -65,6 +77,42 @@ class gempe_params(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("reserved1", ctypes.c_uint32),
     ]
+
+
+class gempe_job_desc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("d", ctypes.c_int32),
+        ("nnz", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col_idx", ctypes.c_void_p),
+        ("X0", ctypes.c_void_p),
+        ("iters", ctypes.c_int32),
+        ("eta", ctypes.c_float),
+        ("params", gempe_params),
+        ("release_s", ctypes.c_double),
+        ("X_out", ctypes.c_void_p),
+        ("loss_hist", ctypes.c_void_p),
+    ]
+
+
+class gempe_job_info(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("batched", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("release_s", ctypes.c_double),
+        ("admit_s", ctypes.c_double),
+        ("done_s", ctypes.c_double),
+        ("footprint", ctypes.c_uint64),
+    ]
+
+
+class gempe_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "done", "failed", "rejected", "ticks",
+                                              "peak_bytes", "max_concurrent", "budget_bytes")] + \
+               [("pairs", ctypes.c_double)]
 
 
 _lib = None
@@ -108,6 +156,20 @@ def load(path: str | None = None):
     lib.gempe_status_string.restype = ctypes.c_char_p
     lib.gempe_last_error.argtypes = []
     lib.gempe_last_error.restype = ctypes.c_char_p
+    lib.gempe_job_footprint.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
+    lib.gempe_job_footprint.restype = ctypes.c_size_t
+    lib.gempe_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.gempe_server_create.restype = st
+    lib.gempe_server_submit.argtypes = [vp, ctypes.POINTER(gempe_job_desc), ctypes.POINTER(ctypes.c_int64)]
+    lib.gempe_server_submit.restype = st
+    lib.gempe_server_query.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(gempe_job_info)]
+    lib.gempe_server_query.restype = st
+    lib.gempe_server_wait.argtypes = [vp, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(gempe_job_info)]
+    lib.gempe_server_wait.restype = st
+    lib.gempe_server_get_stats.argtypes = [vp, ctypes.POINTER(gempe_server_stats)]
+    lib.gempe_server_get_stats.restype = st
+    lib.gempe_server_destroy.argtypes = [vp]
+    lib.gempe_server_destroy.restype = st
     if path is None:
         _lib = lib
     return lib
@@ -267,3 +329,105 @@ def embed(g: Graph, X, iters: int, eta: float, ws=None, params=None, loss_hist=N
     _check(load().gempe_embed(g.handle, int(d), _ptr(X), int(iters), float(eta), _ptr(loss_hist), _ptr(ws),
                               int(ws.numel()), ctypes.byref(p), _stream(stream)))
     return X
+
+
+# ------------------------------------------------------------------------------------
+# serving
+# ------------------------------------------------------------------------------------
+
+def job_footprint(n: int, nnz: int, d: int, iters: int, params: gempe_params | None = None) -> int:
+    p = params or params_default()
+    return int(load().gempe_job_footprint(int(n), int(nnz), int(d), int(iters), ctypes.byref(p)))
+
+
+@dataclass
+class JobInfo:
+    state: int
+    status: int
+    batched: bool
+    release_s: float
+    admit_s: float
+    done_s: float
+    footprint: int
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.release_s
+
+
+def _info(i: gempe_job_info) -> JobInfo:
+    return JobInfo(int(i.state), int(i.status), bool(i.batched), float(i.release_s), float(i.admit_s),
+                   float(i.done_s), int(i.footprint))
+
+
+class Server:
+    """A gempe_server handle.  Inputs are numpy arrays on the host; results are written by
+    the library into numpy arrays this object keeps per job until `result` is called."""
+
+    def __init__(self, budget_bytes: int, max_jobs: int = 256):
+        h = ctypes.c_void_p()
+        _check(load().gempe_server_create(int(budget_bytes), int(max_jobs), ctypes.byref(h)))
+        self.handle = h
+        self._out = {}
+
+    def submit(self, n, row_ptr, col_idx, X0, iters: int, eta: float, params=None, release_s: float = 0.0,
+               want_hist: bool = True) -> int:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        x0 = np.ascontiguousarray(X0, dtype=np.float32)
+        d = int(x0.shape[1])
+        X_out = np.empty_like(x0)
+        hist = np.empty(int(iters) + 1, dtype=np.float64) if want_hist else None
+        desc = gempe_job_desc()
+        desc.n = int(n)
+        desc.d = d
+        desc.nnz = int(ci.size)
+        desc.row_ptr = rp.ctypes.data
+        desc.col_idx = ci.ctypes.data if ci.size else None
+        desc.X0 = x0.ctypes.data
+        desc.iters = int(iters)
+        desc.eta = float(eta)
+        desc.params = params or params_default()
+        desc.release_s = float(release_s)
+        desc.X_out = X_out.ctypes.data
+        desc.loss_hist = hist.ctypes.data if hist is not None else None
+        jid = ctypes.c_int64()
+        _check(load().gempe_server_submit(self.handle, ctypes.byref(desc), ctypes.byref(jid)))
+        self._out[int(jid.value)] = (X_out, hist)
+        return int(jid.value)
+
+    def query(self, job_id: int) -> JobInfo:
+        i = gempe_job_info()
+        _check(load().gempe_server_query(self.handle, int(job_id), ctypes.byref(i)))
+        return _info(i)
+
+    def wait(self, job_id: int = -1, timeout_s: float = -1.0) -> JobInfo | None:
+        i = gempe_job_info()
+        _check(load().gempe_server_wait(self.handle, int(job_id), float(timeout_s), ctypes.byref(i)))
+        return _info(i) if job_id >= 0 else None
+
+    def result(self, job_id: int):
+        """(final coordinates, loss history) of a finished job."""
+        return self._out[int(job_id)]
+
+    def stats(self) -> dict:
+        s = gempe_server_stats()
+        _check(load().gempe_server_get_stats(self.handle, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in gempe_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _check(load().gempe_server_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -62,3 +62,21 @@ def test_host_side_argument_checks(lib):
         gempe.GEMPE_ERR_ARG
     assert lib.gempe_graph_num_edges(None) == -1 and lib.gempe_graph_num_vertices(None) == -1
     assert lib.gempe_graph_destroy(None) == gempe.GEMPE_ERR_ARG
+
+
+def test_server_structs_and_host_checks(lib):
+    assert ctypes.sizeof(gempe.gempe_job_desc) == 4 + 4 + 8 + 3 * 8 + 4 + 4 + 40 + 8 + 8 + 8
+    assert ctypes.sizeof(gempe.gempe_job_info) == 16 + 24 + 8
+    p = gempe.params_default()
+    # footprints are pure host arithmetic: graph + X + history + workspace, monotone in n
+    f1 = lib.gempe_job_footprint(1000, 10000, 2, 200, ctypes.byref(p))
+    f2 = lib.gempe_job_footprint(2000, 10000, 2, 200, ctypes.byref(p))
+    assert 0 < f1 < f2
+    assert f1 >= 1000 * 2 * 4 * 6 + 8 * 1001 + 4 * 10000 * 2 + 8 * 201
+    assert lib.gempe_job_footprint(1, 0, 2, 200, ctypes.byref(p)) == 0
+    assert lib.gempe_job_footprint(1000, 10000, 0, 200, ctypes.byref(p)) == 0
+    out = ctypes.c_void_p()
+    assert lib.gempe_server_create(1 << 20, 0, ctypes.byref(out)) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_server_create(1 << 20, 4, None) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_server_submit(None, None, None) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_server_destroy(None) == gempe.GEMPE_ERR_ARG

@@ -1,4 +1,4 @@
-"""gempe_embed (one persistent launch for small n) against the step-by-step path and the
+"""gempe_embed (one fused launch per iteration for small n) against the step-by-step path and the
 FP64 oracle trajectory."""
 from __future__ import annotations
 
