@@ -31,6 +31,90 @@ def flops_per_pair(d: int) -> int:
     return 7 * d + 31
 
 
+def serving_bench(num_jobs: int, load: float, budget_gib: float, oracle_every: int, oracle_max_n: int):
+    """The serving mix: Poisson stream of `num_jobs` embedding requests (n log-uniform in
+    [500, 50000], ER or Chung-Lu with mean degree U[8, 30], d in {2, 16, 128}, 200
+    iterations, BF16 Gram for d >= 64).  Pass 1 releases every job at once and measures the
+    capacity (jobs/s); pass 2 replays the stream's arrival times scaled to load x capacity
+    and reports throughput and the latency (arrival -> result on the host) percentiles."""
+    import numpy as np
+
+    from paper_2011_03479_amd import gempe, synth
+
+    t0 = time.perf_counter()
+    jobs = synth.serving_stream(num_jobs, 1.0)   # arrival times for rate 1 / s, rescaled below
+    gen_s = time.perf_counter() - t0
+    pairs = [j.graph.n * (j.graph.n - 1) // 2 * j.iters for j in jobs]
+    budget = int(budget_gib * (1 << 30))
+
+    def params(j):
+        return gempe.params_default(precision=gempe.GEMPE_BF16_GRAM if j.precision == "bf16" else gempe.GEMPE_FP32)
+
+    def run(release):
+        with gempe.Server(budget, max_jobs=256) as srv:
+            ids = [srv.submit(j.graph.n, j.graph.row_ptr, j.graph.col_idx, j.X0, j.iters, j.eta, params=params(j),
+                              release_s=r) for j, r in zip(jobs, release)]
+            srv.wait(-1)
+            infos = [srv.query(i) for i in ids]
+            st = srv.stats()
+            res = [srv.result(i) for i in ids]
+        return infos, st, res
+
+    # warm-up: a few small jobs of each kind (module load, first launches)
+    with gempe.Server(1 << 30) as srv:
+        for d in (2, 16, 128):
+            g = synth.erdos_renyi(600, 10.0, seed=d)
+            srv.submit(g.n, g.row_ptr, g.col_idx, synth.init_embedding(g.n, d, seed=d), 20, 0.1 / 599,
+                       params=gempe.params_default(precision=gempe.GEMPE_BF16_GRAM if d >= 64 else gempe.GEMPE_FP32))
+        srv.wait(-1)
+
+    infos, st1, _ = run([0.0] * num_jobs)
+    assert all(i.state == gempe.GEMPE_JOB_DONE for i in infos), gempe.last_error()
+    makespan = max(i.done_s for i in infos) - min(i.release_s for i in infos)
+    capacity = num_jobs / makespan
+    rate = load * capacity
+    start = 0.05  # leave the submissions time to complete before the first arrival
+    release = [start + j.arrival_s / rate for j in jobs]
+    infos, st2, res = run(release)
+    assert all(i.state == gempe.GEMPE_JOB_DONE for i in infos), gempe.last_error()
+    lat = np.array([i.done_s - i.release_s for i in infos])
+    span = max(i.done_s for i in infos) - min(i.release_s for i in infos)
+
+    # error against the FP64 oracle on sampled jobs: DL at each sampled job's final X
+    import oracle
+
+    oracle.build(force=False)
+    errs = []
+    sampled = [k for k in range(0, num_jobs, oracle_every) if jobs[k].graph.n <= oracle_max_n]
+    for k in sampled:
+        j = jobs[k]
+        X, hist = res[k]
+        ref = oracle.loss_grad(X.astype(np.float64), j.graph.row_ptr, j.graph.col_idx, 1.5, 1.0, want_grad=False)
+        errs.append((j.precision, abs(float(hist[-1]) - ref["loss"]) / abs(ref["loss"])))
+    return {
+        "jobs": num_jobs,
+        "iters_per_job": jobs[0].iters,
+        "load": load,
+        "capacity_jobs_per_s": capacity,
+        "capacity_pairs_per_s": sum(pairs) / makespan,
+        "rate_jobs_per_s": rate,
+        "throughput_jobs_per_s": num_jobs / span,
+        "throughput_pairs_per_s": sum(pairs) / span,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "batched_jobs": int(sum(i.batched for i in infos)),
+        "max_concurrent": int(st2["max_concurrent"]),
+        "ticks": int(st2["ticks"]),
+        "peak_bytes": int(st2["peak_bytes"]),
+        "budget_bytes": int(st2["budget_bytes"]),
+        "oracle_sampled_jobs": len(sampled),
+        "oracle_max_rel_loss_err_fp32": max([e for p, e in errs if p == "fp32"], default=None),
+        "oracle_max_rel_loss_err_bf16": max([e for p, e in errs if p == "bf16"], default=None),
+        "generate_s": gen_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +123,10 @@ def main():
     ap.add_argument("--workload", default="cl3400")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix pass")
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -142,6 +230,8 @@ def main():
             "sample": f"{its} full loss+gradient evaluations of {w.name} at X0 (FP64 brute force over all "
                       f"ordered pairs, OpenMP over rows), {el:.1f} s",
         }
+    if not args.no_serve:
+        result["serving"] = serving_bench(args.serve_jobs, args.serve_load, args.serve_budget_gib, 10, 6000)
     print(json.dumps(result))
 
 
