@@ -139,6 +139,7 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 // Kernel launchers (sweep.hip).
 struct PairParamsHost {
     float mu_s, inv_sigma, c_neg, c_pos;  // see gempe::PairParams
+    float tk_scale, tk_off, slope_k;
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 

@@ -32,6 +32,9 @@ struct PairParams {
     float inv_sigma;  // 1 / sigma
     float c_neg;      // sqrt(2/pi)/2 * d1s,   d1s = -1 / (sigma ln 2)
     float c_pos;      // 1/sqrt(2 pi) * d1s
+    float tk_scale;   // table index scale 16 / sigma   (16 tau = tk_scale delta + tk_off)
+    float tk_off;     // -16 mu / sigma
+    float slope_k;    // ln 2 / sigma
 };
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -79,9 +82,57 @@ __device__ __forceinline__ void pair_eval(float r2, float a, const PairParams &P
     cc = (a * (Rf * rq)) * rinv;
 }
 
-// Non-edge specialisation used by the sweep (a = +1).
+// Non-edge specialisation (a = +1) with the closed-form evaluation above.
 __device__ __forceinline__ void pair_nonedge(float r2, const PairParams &P, float &dl, float &cc) {
     pair_eval(r2, 1.0f, P, dl, cc);
+}
+
+// ------------------------------------------------------------------------------------
+// Non-edge pair from the piecewise-cubic table of L = log2 dl(tau) (ltab.h), staged in LDS
+// as float4 pairs {n0, r0, a1, a2}, {a3, k d1, k d2, k d3} per segment of width 1/16 in
+// tau, with k = ln2 / sigma folded in by the staging:
+//   16 tau = tk_scale delta + tk_off,  segment = floor(16 tau) + zero,  f = fract(16 tau)
+//   dl = 2^n0 2^(r0 + f(a1 + f(a2 + f a3))),  d dl/d delta = dl k (d1 + f(d2 + f d3))
+// Two transcendentals (rsq, exp2) instead of five; 16 tau is exact in FP32, so f carries
+// every bit of tau.  Returns false when tau is outside the table (dl, cc unspecified).
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int floor_to_int(float x) {
+    int k;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(k) : "v"(x));
+    return k;
+}
+
+__device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, const float4 *__restrict__ tab,
+                                                 int zero, unsigned segs, float &dl, float &cc) {
+    float r2c = r2 + kFltMin;
+    float rinv = hw_rsq(r2c);
+    float delta = r2c * rinv;
+    float tk = __builtin_fmaf(delta, P.tk_scale, P.tk_off);
+    float f = __builtin_amdgcn_fractf(tk);
+    const unsigned idx = (unsigned)(floor_to_int(tk) + zero);
+    const bool ok = idx < segs;
+    const unsigned off = ok ? (idx << 5) : 0u;  // byte offset of the segment's two float4
+    const float4 *e = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + off);
+    const float4 A = e[0], B = e[1];
+    float r = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(B.x, f, A.w), f, A.z), f, A.y);
+    float D = __builtin_fmaf(__builtin_fmaf(B.w, f, B.z), f, B.y);
+    dl = __builtin_amdgcn_ldexpf(hw_exp2(r), __float_as_int(A.x));
+    cc = (dl * D) * rinv;
+    return ok;
+}
+
+// The non-edge value every sweep and edge correction of d <= 16 uses: the table where tau
+// is inside it, else (per lane) the closed form.  A deterministic function of r2, so the
+// sweep and the edge pass subtract exactly what the other added.
+__device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,
+                                             int zero, unsigned segs, float &dl, float &cc) {
+    const bool ok = pair_nonedge_tab(r2, P, tab, zero, segs, dl, cc);
+    if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
+        float dl2, cc2;
+        pair_eval(r2, 1.0f, P, dl2, cc2);
+        dl = ok ? dl : dl2;
+        cc = ok ? cc : cc2;
+    }
 }
 
 }  // namespace gempe

@@ -35,10 +35,34 @@
 
 #include "internal.h"
 #include "pairfn.h"
+#include "ltab.h"
 
 namespace gempe {
 
 constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+// The non-edge table (ltab.h) as float4 pairs, staged into LDS by every workgroup that
+// sweeps or corrects edges for d <= 16.
+constexpr int kLtabF4 = 2 * GEMPE_LTAB_SEGS;
+constexpr int kLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
+constexpr unsigned kLtabSegs = GEMPE_LTAB_SEGS;
+
+__device__ __forceinline__ void stage_ltab(float4 *dst, float slope_k) {
+    const float4 *src = reinterpret_cast<const float4 *>(kLtab);
+    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) {
+        float4 v = src[q];
+        if (q & 1) {  // {a3, d1, d2, d3}: the derivative in d/d delta units, ln2 / sigma folded in
+            v.y *= slope_k;
+            v.z *= slope_k;
+            v.w *= slope_k;
+        }
+        dst[q] = v;
+    }
+}
+
+__device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float &dl, float &cc) {
+    nonedge_eval(r2, P, tab, kLtabZero, kLtabSegs, dl, cc);
+}
 
 // Upper-triangle tile t (row-major over I <= J < nt) -> (I, J).
 __device__ inline void tile_of(long long t, int nt, int &I, int &J) {
@@ -116,7 +140,7 @@ template <int D, int R, bool MASK, bool ROWLOSS>
 __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
                                             float (&colacc)[D + (ROWLOSS ? 1 : 0)], float (&gi)[R][D],
                                             float (&li)[R], float &loss, int lane, int dir, int col0, int n,
-                                            int s0, int s1, const PairParams &P) {
+                                            int s0, int s1, const PairParams &P, const float4 *tab) {
     constexpr int NC = D + (ROWLOSS ? 1 : 0);
     for (int s = s0; s < s1; ++s) {
         int j = 0;
@@ -127,7 +151,7 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
             float diff[D];
             float r2 = sqdist<D>(xi[r], xc, diff);
             float dl, cc;
-            pair_nonedge(r2, P, dl, cc);
+            nonedge(r2, P, tab, dl, cc);
             if (MASK) {
                 bool valid = (irow[r] < j) && (j < n);
                 dl = valid ? dl : 0.0f;
@@ -165,11 +189,14 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
     constexpr int NC = D + (ROWLOSS ? 1 : 0);
     __shared__ float cs[W > 1 ? W * 64 * NC : 1];  // per-wave column partials
     __shared__ float lsum[W];
+    __shared__ float4 ltab[kLtabF4];
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
+    stage_ltab(ltab, P.slope_k);
+    __syncthreads();
     int I, J;
     tile_of(t, nt, I, J);
     const int dir = rot_dir(lane);
@@ -213,9 +240,11 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 #pragma unroll
             for (int k = 0; k < D; ++k) xc[k] = (jc < n && k < d) ? X[(size_t)jc * d + k] : 0.0f;
             if (masked)
-                sweep_steps<D, R, true, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P);
+                sweep_steps<D, R, true, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+                                                 ltab);
             else
-                sweep_steps<D, R, false, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P);
+                sweep_steps<D, R, false, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+                                                  ltab);
         }
         // lane l now holds the partial of column c_l(63)
         const int jc = c0 + ((lane + 63 * dir) & 63);
@@ -387,7 +416,8 @@ __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict_
 // has two entries, each updating its own row).
 // ------------------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float (&dg)[D], const PairParams &P) {
+__device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float (&dg)[D], const PairParams &P,
+                                            const float4 *tab) {
     float xi[D], xj[D], diff[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -397,7 +427,7 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
     float r2 = sqdist<D>(xi, xj, diff);
     float dlp, ccp, dln, ccn;
     pair_eval(r2, -1.0f, P, dlp, ccp);
-    pair_eval(r2, 1.0f, P, dln, ccn);
+    nonedge(r2, P, tab, dln, ccn);
     const float dcc = ccp - ccn;
 #pragma unroll
     for (int k = 0; k < D; ++k) dg[k] = dcc * diff[k];
@@ -432,6 +462,9 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
                                                       unsigned long long *hits, PairParams P) {
     __shared__ float wsum[kEdgeBlock / 64];
     __shared__ unsigned whit[kEdgeBlock / 64];
+    __shared__ float4 ltab[kLtabF4];
+    stage_ltab(ltab, P.slope_k);
+    __syncthreads();
     long long e = (long long)blockIdx.x * kEdgeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float dloss = 0.0f, ddl = 0.0f, dcc = 0.0f;
@@ -449,7 +482,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
         }
         float dlp, ccp, dln, ccn;
         pair_eval(r2, -1.0f, P, dlp, ccp);
-        pair_eval(r2, 1.0f, P, dln, ccn);
+        nonedge(r2, P, ltab, dln, ccn);
         dcc = ccp - ccn;
         ddl = dlp - dln;
         if (i < j) {
@@ -665,6 +698,7 @@ struct IterLds {
     float rowp[4][64 * D];  // per-wave partials: plain LDS stores, summed in wave order
     float colp[4][64 * D];
     float wl[4];
+    float4 tab[kLtabF4];
 };
 
 // Iteration k of one gradient-descent run, executed by workgroup b of the run's
@@ -679,6 +713,8 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const long long nd = (long long)a.n * a.d;
+    stage_ltab(L.tab, a.P.slope_k);
+    __syncthreads();
     float *Xs[2] = {a.Xc, a.Xw};
     const float *Xprev = (k == 0) ? a.Xc : Xs[(k - 1) & 1];
     const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
@@ -706,7 +742,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
             if (e < a.nnz) {
                 i = a.coo_row[e];
                 const int j = a.col[e];
-                const float ddl = edge_entry<D>(xv, i, j, dg, a.P);
+                const float ddl = edge_entry<D>(xv, i, j, dg, a.P, L.tab);
                 if (i < j) loss += ddl;
             }
 #pragma unroll
@@ -740,10 +776,10 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
         li[0] = 0.0f;
         if ((I == J) || (col0 + 64 > a.n))
             sweep_steps<D, 1, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
-                                           a.P);
+                                           a.P, L.tab);
         else
             sweep_steps<D, 1, false, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
-                                            a.P);
+                                            a.P, L.tab);
         const int cl = (lane + dir * (s0 + 15)) & 63;  // column whose partial this lane holds
 #pragma unroll
         for (int q = 0; q < D; ++q) {
@@ -848,6 +884,12 @@ __global__ __launch_bounds__(256) void k_iter_batch(const BatchEntry *__restrict
 // Host side: plan, workspace layout, launches.
 // ======================================================================================
 using namespace gempe;
+
+namespace {
+PairParams dev_params(const PairParamsHost &h) {
+    return PairParams{h.mu_s, h.inv_sigma, h.c_neg, h.c_pos, h.tk_scale, h.tk_off, h.slope_k};
+}
+}  // namespace
 
 namespace {
 
@@ -991,6 +1033,9 @@ PairParamsHost gempe_pair_params(const gempe_params *p) {
     h.inv_sigma = (float)(1.0 / p->sigma);
     h.c_neg = (float)(0.39894228040143267794 * d1s);  // sqrt(2/pi)/2
     h.c_pos = (float)(0.39894228040143267794 * d1s);  // 1/sqrt(2 pi)
+    h.tk_scale = (float)(GEMPE_LTAB_INV_H / p->sigma);
+    h.tk_off = (float)(-GEMPE_LTAB_INV_H * p->mu / p->sigma);
+    h.slope_k = (float)(0.69314718055994530942 / p->sigma);
     return h;
 }
 
@@ -1087,7 +1132,7 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
                                   hipStream_t s, bool clear_status, const GramCtx &gc, double *red) {
-    PairParams P{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
+    const PairParams P = dev_params(pph);
     const int n = g->n;
     const long long nd = (long long)n * d;
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counters);
@@ -1169,7 +1214,7 @@ IterArgs make_iter_args(const gempe_graph_s *g, int d, const SweepPlan &plan, fl
     a.units_edge = plan.units_edge;
     a.units = plan.units;
     a.neg_eta = -eta;
-    a.P = PairParams{pph.mu_s, pph.inv_sigma, pph.c_neg, pph.c_pos};
+    a.P = dev_params(pph);
     return a;
 }
 }  // namespace

@@ -253,7 +253,7 @@ def step_size(n: int) -> float:
 
 
 def workload(name: str) -> Workload:
-    """The five workloads: er1k, cl3400, sbm100k, cl1m (and its d=2 / bf16 variants)."""
+    """The workloads: er1k, cl3400, sbm100k, cl1m (and its bf16 and d = 2 variants)."""
     if name == "er1k":  # Erdos-Renyi n=1000, mean degree 10, d=2, 100 iterations
         g = erdos_renyi(1000, 10.0, seed=1)
         return Workload(name, g, 2, init_embedding(1000, 2, 1001), 100, step_size(1000), "fp32")
@@ -263,10 +263,11 @@ def workload(name: str) -> Workload:
     if name == "sbm100k":  # SBM 50 x 2000, p_in 2e-3, p_out 2e-5, d=128, bf16 Gram, 20 iterations
         g = sbm(50, 2000, 2e-3, 2e-5, seed=3)
         return Workload(name, g, 128, init_embedding(g.n, 128, 1003), 20, step_size(g.n), "bf16")
-    if name in ("cl1m", "cl1m_bf16"):  # Chung-Lu n=1e6, mean 20, gamma 2.3, d=16, 5 iterations
+    if name in ("cl1m", "cl1m_bf16", "cl1m_d2"):  # Chung-Lu n=1e6, mean 20, gamma 2.3, d=16, 5 iterations
         g = chung_lu(1_000_000, 20.0, 2.3, seed=4)
         prec = "bf16" if name.endswith("bf16") else "fp32"
-        return Workload(name, g, 16, init_embedding(g.n, 16, 1004), 5, step_size(g.n), prec)
+        d = 2 if name.endswith("d2") else 16   # d2: the drawing dimension on the large graph
+        return Workload(name, g, d, init_embedding(g.n, d, 1004), 5, step_size(g.n), prec)
     raise KeyError(name)
 
 
