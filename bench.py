@@ -31,6 +31,25 @@ def flops_per_pair(d: int) -> int:
     return 7 * d + 31
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed PMC summary, or None
+    when there is none or the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_iter_cl3400_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel") != kernel or rec.get("workload") != workload:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec
+
+
 def serving_bench(num_jobs: int, load: float, budget_gib: float, oracle_every: int, oracle_max_n: int):
     """The serving mix: Poisson stream of `num_jobs` embedding requests (n log-uniform in
     [500, 50000], ER or Chung-Lu with mean degree U[8, 30], d in {2, 16, 128}, 200
@@ -124,10 +143,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix pass")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 20 times (the reference "
+                         "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        torch.cuda.set_device(0)
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 20}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
@@ -207,6 +240,13 @@ def main():
         "wall_s": wall,
         "final_loss_bits": None,
     }
+    tr = measured_traffic("gempe::k_iter<2>", w.name) if plan_kernel.startswith("k_iter") and d == 2 else None
+    if tr is not None:
+        result["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
+        result["roofline"]["traffic_detail"] = {
+            "unit": "bytes per launch", "fetch": tr["fetch_bytes_per_launch"], "write": tr["write_bytes_per_launch"],
+            "fetch_factor": tr["fetch_factor"], "write_factor": tr["write_factor"],
+            "source": "profiles/k_iter_cl3400_traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)"}
     hist = torch.empty(1, dtype=torch.float64, device="cuda")
     gempe.loss_grad(G, X, ws=ws, params=params, out=gempe.LossGrad(hist, None, None, None))
     torch.cuda.synchronize()

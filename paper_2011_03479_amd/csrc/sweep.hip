@@ -160,9 +160,8 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
             loss += dl;
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                float f = cc * diff[k];
-                gi[r][k] += f;
-                tc[k] = (r == 0) ? f : tc[k] + f;
+                gi[r][k] = __builtin_fmaf(cc, diff[k], gi[r][k]);
+                tc[k] = (r == 0) ? cc * diff[k] : __builtin_fmaf(cc, diff[k], tc[k]);
             }
             if (ROWLOSS) {
                 li[r] += dl;
