@@ -157,6 +157,34 @@ gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, floa
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Weighted majorization (Sec. II-C).  For each pair the parabola w_ij (delta - d_ij)^2 that
+ * matches dl's slope and curvature at the current distance (Eqs. 3-4) has
+ *   w_ij = dl''(delta_ij) / 2 = R (R + tau) / (2 sigma^2 ln 2),  R = phi(tau) / Phi(tau)
+ * (the printed Eq. 3 carries a factor 2/(pi ln 2) where matching the curvature gives
+ * 1/(pi ln 2); this library follows the derivation), and the update of Eq. 5,
+ *   x_i <- y_i / z_i,  z_i = sum_{j != i} w_ij,
+ * equals x_i - g_i / (2 z_i) with g the gradient of DL.  All w_ij > 0.
+ * ------------------------------------------------------------------------------------ */
+
+/* DL, gradient and z_i at X (z: float32[n], required; grad may be NULL).  Same arithmetic
+ * and precision options as gempe_loss_grad; with GEMPE_BF16_GRAM the far non-edges the
+ * screen skips add 0 to z (each would add < 7e-18).  Asynchronous. */
+gempe_status gempe_wm_terms(gempe_graph g, int32_t d, const float *X, float *grad, float *z, double *loss,
+                            void *ws, size_t ws_bytes, const gempe_params *p, hipStream_t stream);
+
+/* One weighted-majorization step (Eq. 5) in place; loss_before (nullable) receives DL at the
+ * X on entry.  A vertex with z_i <= 0 (every weight underflowed) keeps its coordinates.
+ * Asynchronous. */
+gempe_status gempe_wm_step(gempe_graph g, int32_t d, float *X, double *loss_before, void *ws, size_t ws_bytes,
+                           const gempe_params *p, hipStream_t stream);
+
+/* iters weighted-majorization steps at fixed mu, sigma (the loop the paper states for a
+ * fixed sigmoid setting, Sec. II-C); loss_hist as in gempe_embed.  Synchronises once at the
+ * end; GEMPE_ERR_NUMERIC if a non-finite loss appeared. */
+gempe_status gempe_embed_wm(gempe_graph g, int32_t d, float *X, int32_t iters, double *loss_hist, void *ws,
+                            size_t ws_bytes, const gempe_params *p, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Serving: a request loop that runs many embedding jobs (each one gempe_embed-style
  * gradient-descent run on its own graph) on one GPU with continuous batching.
  *

@@ -190,3 +190,15 @@ def wm_update(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0):
     n = np.asarray(X).shape[0]
     r = rows(X, row_ptr, col_idx, np.arange(n), mu, sigma, wm=True)
     return r["y"] / r["z"][:, None], r
+
+
+def wm_trajectory(X0, row_ptr, col_idx, iters: int, mu: float = 1.5, sigma: float = 1.0):
+    """Weighted-majorization iterations at fixed mu, sigma (Sec. II-C: parabola parameters for
+    every pair, then Eq. 5 for every vertex), FP64.  Returns (loss history, final X)."""
+    X = np.array(X0, dtype=np.float64)
+    hist = []
+    for k in range(iters + 1):
+        hist.append(loss_grad(X, row_ptr, col_idx, mu, sigma, want_grad=False)["loss"])
+        if k < iters:
+            X, _ = wm_update(X, row_ptr, col_idx, mu, sigma)
+    return np.array(hist), X

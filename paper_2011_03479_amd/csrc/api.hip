@@ -132,8 +132,9 @@ extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta
 
 hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepPlan &plan, const WsLayout &L,
                                      unsigned char *w, float *X, int iters, float eta, double *loss_hist,
-                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end) {
+                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end, bool wm) {
     float *G = reinterpret_cast<float *>(w + L.gbuf);
+    float *Z = wm ? reinterpret_cast<float *>(w + L.zbuf) : nullptr;
     float *part = reinterpret_cast<float *>(w + L.partials);
     double *scratch_loss = reinterpret_cast<double *>(w + L.counters + 16);
     const PairParamsHost pp = gempe_pair_params(p);
@@ -145,9 +146,13 @@ hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepP
         if (last && !loss_hist) break;
         double *lossp = loss_hist ? loss_hist + k : scratch_loss;
         hipError_t e = gempe_launch_loss_grad(g, d, plan, X, G, nullptr, part, w + L.counters, lossp, nullptr, pp,
-                                              stream, k == 0, gc, reinterpret_cast<double *>(w + L.red));
+                                              stream, k == 0, gc, reinterpret_cast<double *>(w + L.red),
+                                              last ? nullptr : Z);
         if (e != hipSuccess) return e;
-        if (!last && (e = gempe_launch_axpy(X, G, eta, nd, stream)) != hipSuccess) return e;
+        if (!last) {
+            e = wm ? gempe_launch_wm_update(X, G, Z, d, nd, stream) : gempe_launch_axpy(X, G, eta, nd, stream);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -171,11 +176,72 @@ extern "C" gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t 
         // one fused launch per iteration
         GEMPE_HIP_TRY(gempe_launch_embed_fused(g, d, plan, X, iters, eta, loss_hist, L, w, pp, stream));
     } else {
-        GEMPE_HIP_TRY(gempe_enqueue_embed_steps(g, d, plan, L, w, X, iters, eta, loss_hist, p, stream, 0, iters + 1));
+        GEMPE_HIP_TRY(
+            gempe_enqueue_embed_steps(g, d, plan, L, w, X, iters, eta, loss_hist, p, stream, 0, iters + 1, false));
     }
     unsigned host_status = 0;
     GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
     GEMPE_HIP_TRY(hipStreamSynchronize(stream));
     if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed: non-finite loss");
+    return GEMPE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Weighted majorization (Sec. II-C, Eqs. 3-5)
+// ------------------------------------------------------------------------------------
+
+extern "C" gempe_status gempe_wm_terms(gempe_graph g, int32_t d, const float *X, float *grad, float *z,
+                                       double *loss, void *ws, size_t ws_bytes, const gempe_params *p,
+                                       hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "wm_terms");
+    if (st != GEMPE_OK) return st;
+    if (!X || !z || !loss) return gempe_fail(GEMPE_ERR_ARG, "wm_terms: X, z and loss are required");
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
+    WsLayout L = gempe_ws_layout(g, d, plan);
+    if ((st = check_ws(g, d, ws, ws_bytes, L, "wm_terms")) != GEMPE_OK) return st;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    float *G = grad ? grad : reinterpret_cast<float *>(w + L.gbuf);
+    GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, reinterpret_cast<float *>(w + L.partials),
+                                         w + L.counters, loss, nullptr, gempe_pair_params(p), stream, true,
+                                         gempe_gram_ctx(L, w, p), reinterpret_cast<double *>(w + L.red), z));
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_wm_step(gempe_graph g, int32_t d, float *X, double *loss_before, void *ws,
+                                      size_t ws_bytes, const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "wm_step");
+    if (st != GEMPE_OK) return st;
+    if (!X) return gempe_fail(GEMPE_ERR_ARG, "wm_step: X is required");
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
+    WsLayout L = gempe_ws_layout(g, d, plan);
+    if ((st = check_ws(g, d, ws, ws_bytes, L, "wm_step")) != GEMPE_OK) return st;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    float *G = reinterpret_cast<float *>(w + L.gbuf);
+    float *Z = reinterpret_cast<float *>(w + L.zbuf);
+    double *lossp = loss_before ? loss_before : reinterpret_cast<double *>(w + L.counters + 16);
+    GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, reinterpret_cast<float *>(w + L.partials),
+                                         w + L.counters, lossp, nullptr, gempe_pair_params(p), stream, true,
+                                         gempe_gram_ctx(L, w, p), reinterpret_cast<double *>(w + L.red), Z));
+    GEMPE_HIP_TRY(gempe_launch_wm_update(X, G, Z, d, (long long)g->n * d, stream));
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_embed_wm(gempe_graph g, int32_t d, float *X, int32_t iters, double *loss_hist,
+                                       void *ws, size_t ws_bytes, const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "embed_wm");
+    if (st != GEMPE_OK) return st;
+    if (!X) return gempe_fail(GEMPE_ERR_ARG, "embed_wm: X is required");
+    if (iters < 0) return gempe_fail(GEMPE_ERR_ARG, "embed_wm: iters must be >= 0");
+    SweepPlan plan = gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM);
+    WsLayout L = gempe_ws_layout(g, d, plan);
+    if ((st = check_ws(g, d, ws, ws_bytes, L, "embed_wm")) != GEMPE_OK) return st;
+    if (iters == 0 && !loss_hist) return GEMPE_OK;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    unsigned *status_ws = reinterpret_cast<unsigned *>(w + L.counters + 8);
+    GEMPE_HIP_TRY(gempe_enqueue_embed_steps(g, d, plan, L, w, X, iters, 1.0f, loss_hist, p, stream, 0, iters + 1, true));
+    unsigned host_status = 0;
+    GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+    if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_wm: non-finite loss");
     return GEMPE_OK;
 }

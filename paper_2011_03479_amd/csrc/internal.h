@@ -119,6 +119,7 @@ struct WsLayout {
     size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, ...
     size_t partials = 0;  // float[plan.partials]
     size_t gbuf = 0;      // float[n*d] gradient scratch for gempe_step/gempe_embed
+    size_t zbuf = 0;      // float[n] weighted-majorization denominators z_i
     size_t xbuf = 0;      // float[n*d] embed: second slot of the double-buffered iterate
     size_t gring = 0;     // float[3*n*d] embed: three gradient slots
     size_t ppart = 0;     // float[2*plan.units] embed: double-buffered loss partials
@@ -139,7 +140,7 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 // Kernel launchers (sweep.hip).
 struct PairParamsHost {
     float mu_s, inv_sigma, c_neg, c_pos;  // see gempe::PairParams
-    float tk_scale, tk_off, slope_k;
+    float tk_scale, tk_off, slope_k, r_scale, w_scale, wk2;
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 
@@ -157,11 +158,12 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   const float *X, float *grad, float *row_loss, float *partials,
                                   unsigned char *counters, double *loss, int64_t *hits_out,
                                   const PairParamsHost &pp, hipStream_t s, bool clear_status,
-                                  const GramCtx &gc, double *red);
+                                  const GramCtx &gc, double *red, float *wm_z = nullptr);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
+hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s);
 // Continuous batching of fused iterations (sweep.hip): one table row per job.
 size_t gempe_batch_entry_bytes();
 void gempe_batch_entry_fill(void *dst, const gempe_graph_s *g, int d, const SweepPlan &plan, float *X,
@@ -177,8 +179,10 @@ hipError_t gempe_launch_embed_fused(const gempe_graph_s *g, int d, const SweepPl
                                          const PairParamsHost &pp, hipStream_t s);
 
 // Enqueues iterations [k_begin, k_end) of a run that is not fused (an evaluation of the loss
-// and gradient followed by the step; k = iters is the final loss-only evaluation when
-// loss_hist is given).  k = 0 clears the status word.  Nothing is synchronised (api.hip).
+// and gradient followed by the step: X - eta G, or with wm the weighted-majorization update
+// X - G / (2 z); k = iters is the final loss-only evaluation when loss_hist is given).  k = 0
+// clears the status word.  Nothing is synchronised (api.hip).
 hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepPlan &plan, const WsLayout &L,
                                      unsigned char *w, float *X, int iters, float eta, double *loss_hist,
-                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end);
+                                     const gempe_params *p, hipStream_t stream, int k_begin, int k_end,
+                                     bool wm = false);

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "erfcx_coef.h"
+#include "millsq_coef.h"
 
 namespace gempe {
 
@@ -35,6 +36,9 @@ struct PairParams {
     float tk_scale;   // table index scale 16 / sigma   (16 tau = tk_scale delta + tk_off)
     float tk_off;     // -16 mu / sigma
     float slope_k;    // ln 2 / sigma
+    float r_scale;    // -sigma ln 2          (R = phi/Phi from the slope term)
+    float w_scale;    // 1 / (2 sigma^2 ln 2) (w = dl''/2 = R (R + tau) w_scale)
+    float wk2;        // -1 / (32 sigma)      (table form of w, see pair_nonedge_tab)
 };
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -47,9 +51,14 @@ __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 
-// dl (bits) and cc for squared distance r2; a = +1 (non-edge) or -1 (edge).
-__device__ __forceinline__ void pair_eval(float r2, float a, const PairParams &P, float &dl,
-                                          float &cc) {
+// dl (bits) and cc for squared distance r2; a = +1 (non-edge) or -1 (edge).  With W, also
+// the weight of the weighted-majorization parabola (Sec. II-C, Eqs. 3-4: slope and curvature
+// of the parabola match dl at the current distance), w = dl''/2 = R (R + tau) / (2 sigma^2
+// ln 2).  For tau < 0, R + tau = R q(-tau) with q(t) = 1 - t M(t) (M the Mills ratio) from
+// millsq_coef.h, so far edges (R + tau -> 1/|tau|) keep full relative accuracy.
+template <bool W>
+__device__ __forceinline__ void pair_eval_t(float r2, float a, const PairParams &P, float &dl, float &cc,
+                                            float &w) {
     // FLT_MIN keeps rsq finite at r2 = 0 and leaves every r2 > 2^-102 unchanged; NaN and
     // infinite r2 stay non-finite and reach the loss (and the status word).
     float r2c = r2 + kFltMin;
@@ -80,6 +89,20 @@ __device__ __forceinline__ void pair_eval(float r2, float a, const PairParams &P
     dl = -(hw_log2(sel) + (neg ? nu2l : corr));
     float Rf = neg ? P.c_neg : E * P.c_pos;
     cc = (a * (Rf * rq)) * rinv;
+    if (W) {
+        const float R = (Rf * rq) * P.r_scale;      // phi(tau) / Phi(tau)
+        float fq = kMillsQCoef[GEMPE_MILLSQ_NCOEF - 1];
+#pragma unroll
+        for (int k = GEMPE_MILLSQ_NCOEF - 2; k >= 0; --k) fq = __builtin_fmaf(fq, y, kMillsQCoef[k]);
+        const float wn = (R * R) * (fq * hw_rcp(__builtin_fmaf(t, t, 1.0f)));
+        const float wp = R * (R + tau);
+        w = (neg ? wn : wp) * P.w_scale;
+    }
+}
+
+__device__ __forceinline__ void pair_eval(float r2, float a, const PairParams &P, float &dl, float &cc) {
+    float unused;
+    pair_eval_t<false>(r2, a, P, dl, cc, unused);
 }
 
 // Non-edge specialisation (a = +1) with the closed-form evaluation above.
@@ -102,8 +125,9 @@ __device__ __forceinline__ int floor_to_int(float x) {
     return k;
 }
 
+template <bool W>
 __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, const float4 *__restrict__ tab,
-                                                 int zero, unsigned segs, float &dl, float &cc) {
+                                                 int zero, unsigned segs, float &dl, float &cc, float &w) {
     float r2c = r2 + kFltMin;
     float rinv = hw_rsq(r2c);
     float delta = r2c * rinv;
@@ -117,21 +141,26 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
     float r = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(B.x, f, A.w), f, A.z), f, A.y);
     float D = __builtin_fmaf(__builtin_fmaf(B.w, f, B.z), f, B.y);
     dl = __builtin_amdgcn_ldexpf(hw_exp2(r), __float_as_int(A.x));
-    cc = (dl * D) * rinv;
+    const float c1 = dl * D;  // d dl / d delta
+    cc = c1 * rinv;
+    // w = R (R + tau) / (2 sigma^2 ln 2) with R = -sigma ln2 c1:  w = c1 (ln2/2 c1 - tau/(2 sigma))
+    if (W) w = c1 * __builtin_fmaf(0.34657359028f, c1, tk * P.wk2);
     return ok;
 }
 
 // The non-edge value every sweep and edge correction of d <= 16 uses: the table where tau
 // is inside it, else (per lane) the closed form.  A deterministic function of r2, so the
 // sweep and the edge pass subtract exactly what the other added.
+template <bool W>
 __device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,
-                                             int zero, unsigned segs, float &dl, float &cc) {
-    const bool ok = pair_nonedge_tab(r2, P, tab, zero, segs, dl, cc);
+                                             int zero, unsigned segs, float &dl, float &cc, float &w) {
+    const bool ok = pair_nonedge_tab<W>(r2, P, tab, zero, segs, dl, cc, w);
     if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
-        float dl2, cc2;
-        pair_eval(r2, 1.0f, P, dl2, cc2);
+        float dl2, cc2, w2;
+        pair_eval_t<W>(r2, 1.0f, P, dl2, cc2, w2);
         dl = ok ? dl : dl2;
         cc = ok ? cc : cc2;
+        if (W) w = ok ? w : w2;
     }
 }
 

@@ -60,9 +60,16 @@ __device__ __forceinline__ void stage_ltab(float4 *dst, float slope_k) {
     }
 }
 
-__device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float &dl, float &cc) {
-    nonedge_eval(r2, P, tab, kLtabZero, kLtabSegs, dl, cc);
+template <bool W = false>
+__device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float &dl, float &cc,
+                                        float &w) {
+    nonedge_eval<W>(r2, P, tab, kLtabZero, kLtabSegs, dl, cc, w);
 }
+
+// What the per-vertex "extra" output of a sweep accumulates (the array called rowloss /
+// extra in the kernels): nothing, the row loss L_i = sum_j dl_ij, or the weighted-
+// majorization denominator z_i = sum_j w_ij (Eq. 5).
+constexpr int kExNone = 0, kExRowLoss = 1, kExZ = 2;
 
 // Upper-triangle tile t (row-major over I <= J < nt) -> (I, J).
 __device__ inline void tile_of(long long t, int nt, int &I, int &J) {
@@ -136,12 +143,12 @@ __device__ __forceinline__ float sqdist(const float (&a)[D], const float (&b)[D]
 // it holds the partial of column c_l(s-1) = c_{l-dir}(s), so rotating it by one lane
 // realigns it with c_l(s), and the rotation and this step's addition are one DPP add.
 // After the last step lane l holds the partial of column c_l(s1 - 1).
-template <int D, int R, bool MASK, bool ROWLOSS>
+template <int D, int R, bool MASK, int EX>
 __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
-                                            float (&colacc)[D + (ROWLOSS ? 1 : 0)], float (&gi)[R][D],
+                                            float (&colacc)[D + (EX != 0 ? 1 : 0)], float (&gi)[R][D],
                                             float (&li)[R], float &loss, int lane, int dir, int col0, int n,
                                             int s0, int s1, const PairParams &P, const float4 *tab) {
-    constexpr int NC = D + (ROWLOSS ? 1 : 0);
+    constexpr int NC = D + (EX != 0 ? 1 : 0);
     for (int s = s0; s < s1; ++s) {
         int j = 0;
         if (MASK) j = col0 + ((lane + dir * s) & 63);
@@ -150,12 +157,13 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
         for (int r = 0; r < R; ++r) {
             float diff[D];
             float r2 = sqdist<D>(xi[r], xc, diff);
-            float dl, cc;
-            nonedge(r2, P, tab, dl, cc);
+            float dl, cc, w = 0.0f;
+            nonedge<EX == kExZ>(r2, P, tab, dl, cc, w);
             if (MASK) {
                 bool valid = (irow[r] < j) && (j < n);
                 dl = valid ? dl : 0.0f;
                 cc = valid ? cc : 0.0f;
+                w = valid ? w : 0.0f;
             }
             loss += dl;
 #pragma unroll
@@ -163,9 +171,10 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
                 gi[r][k] = __builtin_fmaf(cc, diff[k], gi[r][k]);
                 tc[k] = (r == 0) ? cc * diff[k] : __builtin_fmaf(cc, diff[k], tc[k]);
             }
-            if (ROWLOSS) {
-                li[r] += dl;
-                tc[NC - 1] = (r == 0) ? dl : tc[NC - 1] + dl;
+            if (EX) {
+                const float ex = (EX == kExZ) ? w : dl;
+                li[r] += ex;
+                tc[NC - 1] = (r == 0) ? ex : tc[NC - 1] + ex;
             }
         }
 #pragma unroll
@@ -178,14 +187,14 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
 // ------------------------------------------------------------------------------------
 // Register-resident sweep, d <= 16, one launch per evaluation.
 // ------------------------------------------------------------------------------------
-template <int D, int R, int W, bool ROWLOSS>
+template <int D, int R, int W, int EX>
 __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict__ X, int n, int d,
                                                         int nt, long long items, long long per_xcd,
                                                         float *__restrict__ G,
                                                         float *__restrict__ rowloss,
                                                         float *__restrict__ partials, PairParams P) {
     constexpr int T = 64 * R * W;
-    constexpr int NC = D + (ROWLOSS ? 1 : 0);
+    constexpr int NC = D + (EX != 0 ? 1 : 0);
     __shared__ float cs[W > 1 ? W * 64 * NC : 1];  // per-wave column partials
     __shared__ float lsum[W];
     __shared__ float4 ltab[kLtabF4];
@@ -239,10 +248,10 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 #pragma unroll
             for (int k = 0; k < D; ++k) xc[k] = (jc < n && k < d) ? X[(size_t)jc * d + k] : 0.0f;
             if (masked)
-                sweep_steps<D, R, true, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+                sweep_steps<D, R, true, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
                                                  ltab);
             else
-                sweep_steps<D, R, false, ROWLOSS>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+                sweep_steps<D, R, false, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
                                                   ltab);
         }
         // lane l now holds the partial of column c_l(63)
@@ -252,7 +261,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 #pragma unroll
                 for (int k = 0; k < D; ++k)
                     if (k < d) atomicAdd(&G[(size_t)jc * d + k], -colacc[k]);
-                if (ROWLOSS) atomicAdd(&rowloss[jc], colacc[NC - 1]);
+                if (EX) atomicAdd(&rowloss[jc], colacc[NC - 1]);
             }
         } else {
 #pragma unroll
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                 if (j < n) {
                     if (dd < D) {
                         if (dd < d) atomicAdd(&G[(size_t)j * d + dd], -v);
-                    } else if (ROWLOSS) {
+                    } else if (EX) {
                         atomicAdd(&rowloss[j], v);
                     }
                 }
@@ -286,7 +295,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 #pragma unroll
             for (int k = 0; k < D; ++k)
                 if (k < d) atomicAdd(&G[(size_t)irow[r] * d + k], gi[r][k]);
-            if (ROWLOSS) atomicAdd(&rowloss[irow[r]], li[r]);
+            if (EX) atomicAdd(&rowloss[irow[r]], li[r]);
         }
     }
     float ws = wave_sum(loss_acc);
@@ -307,7 +316,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 // FLUSH (BF16 screen's exact pass only): a step whose 64 exact distances all satisfy
 // delta^2 >= far2 = (mu + near_k sigma)^2 skips the pair function and the gradient: those
 // pairs are far non-edges, flushed exactly as the screen flushes them.
-template <int D, bool ROWLOSS, bool FLUSH>
+template <int D, int EX, bool FLUSH>
 __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int J, float *__restrict__ G,
                            float *__restrict__ rowloss, const PairParams &P, float *lds, float far2) {
     constexpr int S = D + 1;  // padded stride: lane-private rows hit distinct banks
@@ -340,16 +349,18 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
             r2 = __builtin_fmaf(df, df, r2);
         }
         if (FLUSH && __ballot(!(r2 >= far2)) == 0ull) continue;  // wave-uniform: every pair far
-        float dl, cc;
-        pair_nonedge(r2, P, dl, cc);
+        float dl, cc, w = 0.0f;
+        pair_eval_t<EX == kExZ>(r2, 1.0f, P, dl, cc, w);
         if (masked) {
             bool valid = (i < j) && (j < n);
             dl = valid ? dl : 0.0f;
             cc = valid ? cc : 0.0f;
+            w = valid ? w : 0.0f;
         }
-        if (FLUSH && r2 >= far2) dl = 0.0f, cc = 0.0f;
+        if (FLUSH && r2 >= far2) dl = 0.0f, cc = 0.0f, w = 0.0f;
         loss += dl;
-        if (ROWLOSS) lrow += dl;
+        const float ex = (EX == kExZ) ? w : dl;
+        if (EX) lrow += ex;
         float *ga = gr + lane * S;
         float *gb = gc + c * S;
         for (int k = 0; k < D; ++k) {
@@ -357,7 +368,7 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
             ga[k] += f;
             gb[k] -= f;
         }
-        if (ROWLOSS) gb[D] += dl;  // the pad column carries the column row-loss
+        if (EX) gb[D] += ex;  // the pad column carries the column's extra sum
         // next step reads columns another lane just wrote: keep LDS program order
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -370,15 +381,15 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
         if (dd < d) {
             if (ri < n) atomicAdd(&G[(size_t)ri * d + dd], gr[k]);
             if (cj < n) atomicAdd(&G[(size_t)cj * d + dd], gc[k]);
-        } else if (ROWLOSS && dd == D && cj < n) {
+        } else if (EX && dd == D && cj < n) {
             atomicAdd(&rowloss[cj], gc[k]);
         }
     }
-    if (ROWLOSS && i < n) atomicAdd(&rowloss[i], lrow);
+    if (EX && i < n) atomicAdd(&rowloss[i], lrow);
     return wave_sum(loss);
 }
 
-template <int D, bool ROWLOSS>
+template <int D, int EX>
 __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, int n, int d, int nt,
                                                    long long items, long long per_xcd,
                                                    float *__restrict__ G, float *__restrict__ rowloss,
@@ -388,13 +399,13 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
     if (t >= items) return;
     int I, J;
     tile_of(t, nt, I, J);
-    float l = wide_tile<D, ROWLOSS, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
+    float l = wide_tile<D, EX, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
     if (threadIdx.x == 0) partials[t] = l;
 }
 
 // Exact FP32 pass over the tiles the BF16 screen flagged: list[0..*count) holds upper-
 // triangle 64 x 64 tile indices in increasing order; partial slot q belongs to list[q].
-template <int D, bool ROWLOSS>
+template <int D, int EX>
 __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict__ X, int n, int d, int nt,
                                                         const int *__restrict__ list, const int *__restrict__ count,
                                                         float *__restrict__ G, float *__restrict__ rowloss,
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict_
     for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
         int I, J;
         tile_of(list[q], nt, I, J);
-        float l = wide_tile<D, ROWLOSS, true>(X, n, d, I, J, G, rowloss, P, lds, far2);
+        float l = wide_tile<D, EX, true>(X, n, d, I, J, G, rowloss, P, lds, far2);
         if (threadIdx.x == 0) partials[q] = l;
     }
 }
@@ -424,9 +435,9 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
         xj[k] = k < xv.d ? xv.at(j, k) : 0.0f;
     }
     float r2 = sqdist<D>(xi, xj, diff);
-    float dlp, ccp, dln, ccn;
+    float dlp, ccp, dln, ccn, wn;
     pair_eval(r2, -1.0f, P, dlp, ccp);
-    nonedge(r2, P, tab, dln, ccn);
+    nonedge(r2, P, tab, dln, ccn, wn);
     const float dcc = ccp - ccn;
 #pragma unroll
     for (int k = 0; k < D; ++k) dg[k] = dcc * diff[k];
@@ -450,7 +461,7 @@ __device__ __forceinline__ bool seg_sum_to_head(int key, int lane, float &v) {
 
 constexpr int kEdgeBlock = 256;
 
-template <bool ROWLOSS>
+template <int EX>
 __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ X, int d,
                                                       const int32_t *__restrict__ coo_row,
                                                       const int32_t *__restrict__ col, long long nnz,
@@ -466,7 +477,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     __syncthreads();
     long long e = (long long)blockIdx.x * kEdgeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float dloss = 0.0f, ddl = 0.0f, dcc = 0.0f;
+    float dloss = 0.0f, ddl = 0.0f, dcc = 0.0f, dw = 0.0f;
     unsigned hit = 0;
     int i = -1, j = 0;
     if (e < nnz) {
@@ -479,11 +490,12 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
             float df = xi[k] - xj[k];
             r2 = __builtin_fmaf(df, df, r2);
         }
-        float dlp, ccp, dln, ccn;
-        pair_eval(r2, -1.0f, P, dlp, ccp);
-        nonedge(r2, P, ltab, dln, ccn);
+        float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
+        pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
+        nonedge<EX == kExZ>(r2, P, ltab, dln, ccn, wn);
         dcc = ccp - ccn;
         ddl = dlp - dln;
+        dw = wp - wn;
         if (i < j) {
             dloss = ddl;
             hit = gempe_hash_contains(table, cap, gempe_edge_key(i, j)) ? 1u : 0u;
@@ -494,8 +506,8 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
         float v = (i >= 0) ? dcc * (X[(size_t)i * d + k] - X[(size_t)j * d + k]) : 0.0f;
         if (seg_sum_to_head(i, lane, v)) atomicAdd(&G[(size_t)i * d + k], v);
     }
-    if (ROWLOSS) {
-        float v = ddl;
+    if (EX) {
+        float v = (EX == kExZ) ? dw : ddl;
         if (seg_sum_to_head(i, lane, v)) atomicAdd(&rowloss[i], v);
     }
     float s = wave_sum(dloss);
@@ -519,7 +531,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
 // change stays in registers until one atomic per coordinate.  The squared distance is a
 // wave-wide sum, so it agrees with the sweep's sequential sum to rounding (not bitwise);
 // the residual is a relative 1e-7 of dl- for that edge.
-template <bool ROWLOSS>
+template <int EX>
 __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X, int n, int d,
                                                     const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
@@ -545,14 +557,14 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
             const float df0 = xi0 - (lane < d ? xj[lane] : 0.0f);
             const float df1 = xi1 - (lane + 64 < d ? xj[lane + 64] : 0.0f);
             const float r2 = wave_sum(__builtin_fmaf(df1, df1, df0 * df0));
-            float dlp, ccp, dln, ccn;
-            pair_eval(r2, -1.0f, P, dlp, ccp);
-            pair_eval(r2, 1.0f, P, dln, ccn);
+            float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
+            pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
+            pair_eval_t<EX == kExZ>(r2, 1.0f, P, dln, ccn, wn);
             const float dcc = ccp - ccn;
             g0 += dcc * df0;
             g1 += dcc * df1;
             const float ddl = dlp - dln;
-            if (ROWLOSS) lrow += ddl;
+            if (EX) lrow += (EX == kExZ) ? wp - wn : ddl;
             if (i < j) {
                 dloss += ddl;
                 if (lane == 0 && gempe_hash_contains(table, cap, gempe_edge_key(i, j))) ++hitc;
@@ -560,7 +572,7 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
         }
         if (lane < d) atomicAdd(&G[(size_t)i * d + lane], g0);
         if (lane + 64 < d) atomicAdd(&G[(size_t)i * d + lane + 64], g1);
-        if (ROWLOSS && lane == 0) atomicAdd(&rowloss[i], lrow);
+        if (EX && lane == 0) atomicAdd(&rowloss[i], lrow);
     }
     if (lane == 0) {
         wsum[wave] = dloss;
@@ -644,6 +656,18 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double *__restrict
         if (hits_out) *hits_out = (int64_t)*hits;
         if (!isfinite(sh[0])) atomicOr(status, kStatusNonFinite);
     }
+}
+
+// Weighted-majorization update (Eq. 5): x_i <- y_i / z_i, which equals x_i - g_i / (2 z_i)
+// because y_i = z_i x_i - g_i / 2 (the parabola's slope matches dl' at the current distance).
+// A vertex whose z_i is not positive (every w_ij underflowed, or non-finite input) stays.
+__global__ void k_wm_update(float *__restrict__ X, const float *__restrict__ G, const float *__restrict__ Z,
+                            int d, long long count) {
+    long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const float z = Z[k / d];
+    const float s = (z > 0.0f) ? 0.5f / z : 0.0f;
+    X[k] = __builtin_fmaf(-G[k], s, X[k]);
 }
 
 __global__ void k_axpy(float *__restrict__ X, const float *__restrict__ G, float eta, long long count) {
@@ -886,7 +910,8 @@ using namespace gempe;
 
 namespace {
 PairParams dev_params(const PairParamsHost &h) {
-    return PairParams{h.mu_s, h.inv_sigma, h.c_neg, h.c_pos, h.tk_scale, h.tk_off, h.slope_k};
+    return PairParams{h.mu_s,     h.inv_sigma, h.c_neg,   h.c_pos, h.tk_scale,
+                      h.tk_off,   h.slope_k,   h.r_scale, h.w_scale, h.wk2};
 }
 }  // namespace
 
@@ -985,6 +1010,8 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     off = align256(off + sizeof(float) * (size_t)plan.partials);
     L.gbuf = off;
     off = align256(off + sizeof(float) * nd);
+    L.zbuf = off;
+    off = align256(off + sizeof(float) * (size_t)g->n);
     L.xbuf = off;
     off = align256(off + sizeof(float) * nd);
     L.gring = off;
@@ -1035,84 +1062,87 @@ PairParamsHost gempe_pair_params(const gempe_params *p) {
     h.tk_scale = (float)(GEMPE_LTAB_INV_H / p->sigma);
     h.tk_off = (float)(-GEMPE_LTAB_INV_H * p->mu / p->sigma);
     h.slope_k = (float)(0.69314718055994530942 / p->sigma);
+    h.r_scale = (float)(-p->sigma * 0.69314718055994530942);
+    h.w_scale = (float)(1.0 / (2.0 * p->sigma * p->sigma * 0.69314718055994530942));
+    h.wk2 = (float)(-1.0 / (32.0 * p->sigma));
     return h;
 }
 
 namespace {
 
-template <int D, int R, int W, bool RL>
+template <int D, int R, int W, int EX>
 void launch_small(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, float *G, float *rl,
                   float *part, PairParams P) {
     long long per = pl.grid / kXcd;
-    hipLaunchKernelGGL((k_sweep_small<D, R, W, RL>), dim3((unsigned)pl.grid), dim3(64 * W), 0, s, X, n, d,
+    hipLaunchKernelGGL((k_sweep_small<D, R, W, EX>), dim3((unsigned)pl.grid), dim3(64 * W), 0, s, X, n, d,
                        pl.nt, pl.items, per, G, rl, part, P);
 }
 
-template <int D, bool RL>
+template <int D, int EX>
 void launch_small_rw(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, float *G, float *rl,
                      float *part, PairParams P) {
-    if (pl.R == 1 && pl.W == 1) return launch_small<D, 1, 1, RL>(pl, s, X, n, d, G, rl, part, P);
-    if (pl.R == 1 && pl.W == 2) return launch_small<D, 1, 2, RL>(pl, s, X, n, d, G, rl, part, P);
-    if (pl.R == 1 && pl.W == 4) return launch_small<D, 1, 4, RL>(pl, s, X, n, d, G, rl, part, P);
-    if (pl.R == 2 && pl.W == 4) return launch_small<D, 2, 4, RL>(pl, s, X, n, d, G, rl, part, P);
+    if (pl.R == 1 && pl.W == 1) return launch_small<D, 1, 1, EX>(pl, s, X, n, d, G, rl, part, P);
+    if (pl.R == 1 && pl.W == 2) return launch_small<D, 1, 2, EX>(pl, s, X, n, d, G, rl, part, P);
+    if (pl.R == 1 && pl.W == 4) return launch_small<D, 1, 4, EX>(pl, s, X, n, d, G, rl, part, P);
+    if (pl.R == 2 && pl.W == 4) return launch_small<D, 2, 4, EX>(pl, s, X, n, d, G, rl, part, P);
     if constexpr (D <= 4) {
-        if (pl.R == 4 && pl.W == 4) return launch_small<D, 4, 4, RL>(pl, s, X, n, d, G, rl, part, P);
+        if (pl.R == 4 && pl.W == 4) return launch_small<D, 4, 4, EX>(pl, s, X, n, d, G, rl, part, P);
     }
 }
 
-template <int D, bool RL>
+template <int D, int EX>
 void launch_wide(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, float *G, float *rl,
                  float *part, PairParams P) {
     long long per = pl.grid / kXcd;
     size_t lds = sizeof(float) * 4 * 64 * (D + 1);
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide<D, RL>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide<D, EX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sweep_wide<D, RL>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
+    hipLaunchKernelGGL((k_sweep_wide<D, EX>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
                        pl.items, per, G, rl, part, P);
 }
 
-template <int D, bool RL>
+template <int D, int EX>
 void launch_wide_list(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, const GramCtx &gc,
                       float *G, float *rl, float *part, PairParams P) {
     size_t lds = sizeof(float) * 4 * 64 * (D + 1);
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide_list<D, RL>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sweep_wide_list<D, EX>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_sweep_wide_list<D, RL>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
+    hipLaunchKernelGGL((k_sweep_wide_list<D, EX>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
                        gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0);
 }
 
-template <bool RL>
+template <int EX>
 void launch_list(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, const GramCtx &gc, float *G,
                  float *rl, float *part, PairParams P) {
     switch (pl.D) {
-        case 16: return launch_wide_list<16, RL>(pl, s, X, n, d, gc, G, rl, part, P);
-        case 32: return launch_wide_list<32, RL>(pl, s, X, n, d, gc, G, rl, part, P);
-        case 64: return launch_wide_list<64, RL>(pl, s, X, n, d, gc, G, rl, part, P);
-        default: return launch_wide_list<128, RL>(pl, s, X, n, d, gc, G, rl, part, P);
+        case 16: return launch_wide_list<16, EX>(pl, s, X, n, d, gc, G, rl, part, P);
+        case 32: return launch_wide_list<32, EX>(pl, s, X, n, d, gc, G, rl, part, P);
+        case 64: return launch_wide_list<64, EX>(pl, s, X, n, d, gc, G, rl, part, P);
+        default: return launch_wide_list<128, EX>(pl, s, X, n, d, gc, G, rl, part, P);
     }
 }
 
-template <bool RL>
+template <int EX>
 void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int d, float *G, float *rl,
                   float *part, PairParams P) {
     switch (pl.D) {
-        case 1: return launch_small_rw<1, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 2: return launch_small_rw<2, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 3: return launch_small_rw<3, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 4: return launch_small_rw<4, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 8: return launch_small_rw<8, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 16: return launch_small_rw<16, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 32: return launch_wide<32, RL>(pl, s, X, n, d, G, rl, part, P);
-        case 64: return launch_wide<64, RL>(pl, s, X, n, d, G, rl, part, P);
-        default: return launch_wide<128, RL>(pl, s, X, n, d, G, rl, part, P);
+        case 1: return launch_small_rw<1, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 2: return launch_small_rw<2, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 3: return launch_small_rw<3, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 4: return launch_small_rw<4, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 8: return launch_small_rw<8, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 16: return launch_small_rw<16, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 32: return launch_wide<32, EX>(pl, s, X, n, d, G, rl, part, P);
+        case 64: return launch_wide<64, EX>(pl, s, X, n, d, G, rl, part, P);
+        default: return launch_wide<128, EX>(pl, s, X, n, d, G, rl, part, P);
     }
 }
 
@@ -1127,56 +1157,61 @@ void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_
 
 }  // namespace
 
+namespace {
+// The sweep (or BF16 screen + exact list pass) and the exact edge correction, with the
+// per-vertex extra sum EX into `extra` (row loss or the weighted-majorization z).
+template <int EX>
+void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X, float *grad, float *extra,
+                 float *partials, unsigned long long *cnt, const PairParams &P, hipStream_t s, const GramCtx &gc) {
+    const int n = g->n;
+    if (plan.bf16)
+        launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
+    else
+        launch_sweep<EX>(plan, s, X, n, d, grad, extra, partials, P);
+    float *epart = partials + plan.items;
+    if (plan.D > 16) {
+        // wide: one wave per CSR row (also writes the partial of rows without edges)
+        hipLaunchKernelGGL((k_edges_rows<EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
+                           g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, cnt, P);
+    } else if (g->nnz > 0) {
+        hipLaunchKernelGGL((k_edges<EX>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
+                           g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad, extra,
+                           epart, cnt, P);
+    } else {
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, epart, (long long)plan.edge_blocks, nullptr, 0LL,
+                           nullptr, 0);
+    }
+}
+}  // namespace
+
 hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X,
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
-                                  hipStream_t s, bool clear_status, const GramCtx &gc, double *red) {
+                                  hipStream_t s, bool clear_status, const GramCtx &gc, double *red, float *wm_z) {
     const PairParams P = dev_params(pph);
     const int n = g->n;
     const long long nd = (long long)n * d;
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counters);
     unsigned *status = reinterpret_cast<unsigned *>(counters + 8);
+    float *extra = wm_z ? wm_z : row_loss;
     {
-        long long big = std::max<long long>(nd, row_loss ? n : 0);
+        long long big = std::max<long long>(nd, extra ? n : 0);
         unsigned blocks = (unsigned)std::min<long long>(4096, std::max<long long>(1, (big + 255) / 256));
-        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, grad, nd, row_loss, row_loss ? (long long)n : 0,
-                           cnt, clear_status ? 2 : 1);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, grad, nd, extra, extra ? (long long)n : 0, cnt,
+                           clear_status ? 2 : 1);
     }
     if (plan.bf16) {
         hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.smax128, gc.flags, gc.list,
                                                 gc.count, gc.theta0, s);
         if (e != hipSuccess) return e;
-        if (row_loss)
-            launch_list<true>(plan, s, X, n, d, gc, grad, row_loss, partials, P);
-        else
-            launch_list<false>(plan, s, X, n, d, gc, grad, row_loss, partials, P);
-    } else if (row_loss) {
-        launch_sweep<true>(plan, s, X, n, d, grad, row_loss, partials, P);
-    } else {
-        launch_sweep<false>(plan, s, X, n, d, grad, row_loss, partials, P);
     }
+    if (wm_z)
+        launch_pass<kExZ>(g, d, plan, X, grad, wm_z, partials, cnt, P, s, gc);
+    else if (row_loss)
+        launch_pass<kExRowLoss>(g, d, plan, X, grad, row_loss, partials, cnt, P, s, gc);
+    else
+        launch_pass<kExNone>(g, d, plan, X, grad, nullptr, partials, cnt, P, s, gc);
     float *epart = partials + plan.items;
-    if (plan.D > 16) {
-        // wide: one wave per CSR row (also writes the partial of rows without edges)
-        if (row_loss)
-            hipLaunchKernelGGL((k_edges_rows<true>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
-                               g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, row_loss, epart, cnt, P);
-        else
-            hipLaunchKernelGGL((k_edges_rows<false>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
-                               g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, row_loss, epart, cnt, P);
-    } else if (g->nnz > 0) {
-        if (row_loss)
-            hipLaunchKernelGGL((k_edges<true>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
-                               g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad,
-                               row_loss, epart, cnt, P);
-        else
-            hipLaunchKernelGGL((k_edges<false>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
-                               g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad,
-                               row_loss, epart, cnt, P);
-    } else {
-        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, epart, (long long)plan.edge_blocks, nullptr, 0LL,
-                           nullptr, 0);
-    }
     // FP64 loss: sweep partials (for the BF16 screen only the flagged tiles' slots) + edge partials
     const long long total = plan.items + plan.edge_blocks;
     const int nb1 = (int)std::min<long long>(kRed1Blocks, std::max<long long>(1, (total + 4095) / 4096));
@@ -1184,6 +1219,12 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
     hipLaunchKernelGGL(k_reduce1, dim3(nb1), dim3(kFinBlock), 0, s, partials, plan.items,
                        plan.bf16 ? gc.count : nullptr, epart, (long long)plan.edge_blocks, chunk, red);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, s, red, nb1, loss, cnt, hits_out, status);
+    return hipGetLastError();
+}
+
+hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s) {
+    unsigned blocks = (unsigned)std::max<long long>(1, (count + 255) / 256);
+    hipLaunchKernelGGL(k_wm_update, dim3(blocks), dim3(256), 0, s, X, G, Z, d, count);
     return hipGetLastError();
 }
 

@@ -42,6 +42,9 @@ ABI_SYMBOLS = (
     "gempe_embed",
     "gempe_status_string",
     "gempe_last_error",
+    "gempe_wm_terms",
+    "gempe_wm_step",
+    "gempe_embed_wm",
     "gempe_job_footprint",
     "gempe_server_create",
     "gempe_server_submit",
@@ -156,6 +159,12 @@ def load(path: str | None = None):
     lib.gempe_status_string.restype = ctypes.c_char_p
     lib.gempe_last_error.argtypes = []
     lib.gempe_last_error.restype = ctypes.c_char_p
+    lib.gempe_wm_terms.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_wm_terms.restype = st
+    lib.gempe_wm_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_wm_step.restype = st
+    lib.gempe_embed_wm.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_embed_wm.restype = st
     lib.gempe_job_footprint.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
     lib.gempe_job_footprint.restype = ctypes.c_size_t
     lib.gempe_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -328,6 +337,45 @@ def embed(g: Graph, X, iters: int, eta: float, ws=None, params=None, loss_hist=N
         ws = workspace(g, d, p)
     _check(load().gempe_embed(g.handle, int(d), _ptr(X), int(iters), float(eta), _ptr(loss_hist), _ptr(ws),
                               int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return X
+
+
+# ------------------------------------------------------------------------------------
+# weighted majorization
+# ------------------------------------------------------------------------------------
+
+def wm_terms(g: Graph, X, ws=None, params=None, want_grad=True, stream=None):
+    """(loss float64[1], grad float32[n, d] or None, z float32[n]) at X."""
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty((n, d), dtype=torch.float32, device="cuda") if want_grad else None
+    z = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(load().gempe_wm_terms(g.handle, int(d), _ptr(X), _ptr(grad), _ptr(z), _ptr(loss), _ptr(ws),
+                                 int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return loss, grad, z
+
+
+def wm_step(g: Graph, X, ws=None, params=None, loss_before=None, stream=None):
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    _check(load().gempe_wm_step(g.handle, int(d), _ptr(X), _ptr(loss_before), _ptr(ws), int(ws.numel()),
+                                ctypes.byref(p), _stream(stream)))
+    return X
+
+
+def embed_wm(g: Graph, X, iters: int, ws=None, params=None, loss_hist=None, stream=None):
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    _check(load().gempe_embed_wm(g.handle, int(d), _ptr(X), int(iters), _ptr(loss_hist), _ptr(ws),
+                                 int(ws.numel()), ctypes.byref(p), _stream(stream)))
     return X
 
 
