@@ -59,6 +59,17 @@ def _bind(path: str):
     lib.oracle_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
                                      ctypes.c_double, dp, dp, i64p, dp, dp]
     lib.oracle_loss_grad.restype = None
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.oracle_histogram.argtypes = [ctypes.c_int, ctypes.c_int, fp, i64p, i32p, ctypes.c_int, ctypes.c_float,
+                                     u64p, u64p]
+    lib.oracle_histogram.restype = None
+    lib.oracle_sigma_hist.argtypes = [ctypes.c_int, ctypes.c_double, u64p, u64p, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_sigma_hist.restype = ctypes.c_double
+    lib.oracle_sigma_exact.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_sigma_exact.restype = ctypes.c_double
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     return lib
@@ -202,3 +213,46 @@ def wm_trajectory(X0, row_ptr, col_idx, iters: int, mu: float = 1.5, sigma: floa
         if k < iters:
             X, _ = wm_update(X, row_ptr, col_idx, mu, sigma)
     return np.array(hist), X
+
+
+# ------------------------------------------------------------------------------------
+# slope optimisation (Sec. III-F)
+# ------------------------------------------------------------------------------------
+
+SIGMA_LO, SIGMA_HI, SIGMA_ITERS = 1e-3, 1e3, 200
+
+
+def histogram(X32, row_ptr, col_idx, nbins: int, r2_max: float):
+    """(all-pair counts, edge counts) per squared-distance bin, from single-precision X."""
+    lib = _load()
+    Xf = np.ascontiguousarray(X32, dtype=np.float32)
+    n, d = Xf.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    ha = np.zeros(nbins, dtype=np.uint64)
+    he = np.zeros(nbins, dtype=np.uint64)
+    inv_w = np.float32(nbins / r2_max)
+    lib.oracle_histogram(n, d, Xf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _ptr(rp, ctypes.c_int64),
+                         _ptr(ci, ctypes.c_int32), int(nbins), float(inv_w),
+                         ha.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                         he.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return ha, he
+
+
+def sigma_from_histogram(hist_all, hist_edge, r2_max: float, mu: float = 1.5, lo=SIGMA_LO, hi=SIGMA_HI,
+                         iters=SIGMA_ITERS) -> float:
+    lib = _load()
+    ha = np.ascontiguousarray(hist_all, dtype=np.uint64)
+    he = np.ascontiguousarray(hist_edge, dtype=np.uint64)
+    return float(lib.oracle_sigma_hist(int(ha.size), float(r2_max), ha.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                       he.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), float(mu), float(lo),
+                                       float(hi), int(iters)))
+
+
+def sigma_exact(X, row_ptr, col_idx, mu: float = 1.5, lo=SIGMA_LO, hi=SIGMA_HI, iters=SIGMA_ITERS) -> float:
+    """The sigma where d DL / d sigma = 0 over every pair (FP64, no histogram)."""
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    return float(lib.oracle_sigma_exact(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64),
+                                        _ptr(ci, ctypes.c_int32), float(mu), float(lo), float(hi), int(iters)))

@@ -213,3 +213,136 @@ void oracle_set_num_threads(int t) {
     (void)t;
 #endif
 }
+
+/*
+ * Slope optimisation (Sec. III-F).  mu stays fixed and sigma is chosen where the derivative
+ * of Eq. 2 with respect to sigma vanishes, located by bisection.  With tau = a (delta - mu) /
+ * sigma one has d tau / d sigma = -tau / sigma, so
+ *   d dl / d sigma = (d dl / d tau)(-tau / sigma) = tau R(tau) / (sigma ln 2),
+ * and the condition is F(sigma) = sum_{i<j} tau_ij R(tau_ij) = 0 (F < 0: DL still falls as
+ * sigma grows).  The paper evaluates it on histograms of the pair distances, kept separately
+ * for edges and non-edges, rather than on the pairs.
+ *
+ * Histogram layout (the paper gives none; this is the reading): nbins bins uniform in the
+ * squared distance on [0, r2_max).  A pair's bin is the integer part of
+ * min(r2 * inv_w, nbins - 1), computed in single precision from the single-precision
+ * squared distance accumulated coordinate by coordinate with fused multiply-adds, so that a
+ * device computing in single precision takes the same decision for every pair.  A bin stands
+ * for the distance sqrt((b + 1/2) r2_max / nbins).
+ */
+void oracle_histogram(int n, int d, const float *X, const int64_t *row_ptr, const int32_t *col_idx,
+                      int nbins, float inv_w, uint64_t *hist_all, uint64_t *hist_edge) {
+    memset(hist_all, 0, sizeof(uint64_t) * (size_t)nbins);
+    memset(hist_edge, 0, sizeof(uint64_t) * (size_t)nbins);
+    const float top = (float)(nbins - 1);
+#pragma omp parallel
+    {
+        uint64_t *ha = (uint64_t *)calloc((size_t)nbins, sizeof(uint64_t));
+        uint64_t *he = (uint64_t *)calloc((size_t)nbins, sizeof(uint64_t));
+        unsigned char *flag = (unsigned char *)calloc((size_t)n, 1);
+#pragma omp for schedule(dynamic, 16)
+        for (int i = 0; i < n; ++i) {
+            mark_row(row_ptr, col_idx, i, flag, 1);
+            const float *xi = X + (size_t)i * d;
+            for (int j = i + 1; j < n; ++j) {
+                const float *xj = X + (size_t)j * d;
+                float r2 = 0.0f;
+                for (int k = 0; k < d; ++k) {
+                    float df = xi[k] - xj[k];
+                    r2 = fmaf(df, df, r2);
+                }
+                int b = (int)fminf(r2 * inv_w, top);
+                ha[b] += 1;
+                if (flag[j]) he[b] += 1;
+            }
+            mark_row(row_ptr, col_idx, i, flag, 0);
+        }
+#pragma omp critical
+        for (int b = 0; b < nbins; ++b) {
+            hist_all[b] += ha[b];
+            hist_edge[b] += he[b];
+        }
+        free(ha);
+        free(he);
+        free(flag);
+    }
+}
+
+/* F(sigma) on the histograms: every bin's edges and non-edges at the bin's distance. */
+static double hist_F(double sigma, int nbins, double r2_max, const uint64_t *hist_all,
+                     const uint64_t *hist_edge, double mu) {
+    double F = 0.0;
+    for (int b = 0; b < nbins; ++b) {
+        if (!hist_all[b]) continue;
+        double delta = sqrt((b + 0.5) * r2_max / nbins);
+        double t = (delta - mu) / sigma;          /* tau of a non-edge; an edge has -t */
+        double ne = (double)(hist_all[b] - hist_edge[b]);
+        double e = (double)hist_edge[b];
+        if (ne > 0) F += ne * t * mills_inv(t);
+        if (e > 0) F += e * (-t) * mills_inv(-t);
+    }
+    return F;
+}
+
+/* F(sigma) over every pair (exact distances, no histogram). */
+static double pairs_F(double sigma, int n, int d, const double *X, const int64_t *row_ptr,
+                      const int32_t *col_idx, double mu) {
+    double F = 0.0;
+#pragma omp parallel reduction(+ : F)
+    {
+        unsigned char *flag = (unsigned char *)calloc((size_t)n, 1);
+#pragma omp for schedule(dynamic, 16)
+        for (int i = 0; i < n; ++i) {
+            mark_row(row_ptr, col_idx, i, flag, 1);
+            for (int j = i + 1; j < n; ++j) {
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) {
+                    double df = X[(size_t)i * d + k] - X[(size_t)j * d + k];
+                    r2 += df * df;
+                }
+                double a = flag[j] ? -1.0 : 1.0;
+                double t = a * (sqrt(r2) - mu) / sigma;
+                F += t * mills_inv(t);
+            }
+            mark_row(row_ptr, col_idx, i, flag, 0);
+        }
+        free(flag);
+    }
+    return F;
+}
+
+/* Geometric bisection of F on [lo, hi]; a bracket end is returned when F does not change
+ * sign there (the minimum lies on the boundary of the search interval). */
+static double bisect_sigma(double (*Fn)(double, const void *), const void *ctx, double lo, double hi,
+                           int iters) {
+    if (Fn(lo, ctx) >= 0.0) return lo;
+    if (Fn(hi, ctx) <= 0.0) return hi;
+    for (int it = 0; it < iters; ++it) {
+        double s = sqrt(lo * hi);
+        if (Fn(s, ctx) < 0.0) lo = s; else hi = s;
+    }
+    return sqrt(lo * hi);
+}
+
+struct hist_ctx { int nbins; double r2_max; const uint64_t *all, *edge; double mu; };
+static double hist_fn(double s, const void *c) {
+    const struct hist_ctx *h = (const struct hist_ctx *)c;
+    return hist_F(s, h->nbins, h->r2_max, h->all, h->edge, h->mu);
+}
+struct pairs_ctx { int n, d; const double *X; const int64_t *rp; const int32_t *ci; double mu; };
+static double pairs_fn(double s, const void *c) {
+    const struct pairs_ctx *p = (const struct pairs_ctx *)c;
+    return pairs_F(s, p->n, p->d, p->X, p->rp, p->ci, p->mu);
+}
+
+double oracle_sigma_hist(int nbins, double r2_max, const uint64_t *hist_all, const uint64_t *hist_edge,
+                         double mu, double lo, double hi, int iters) {
+    struct hist_ctx c = {nbins, r2_max, hist_all, hist_edge, mu};
+    return bisect_sigma(hist_fn, &c, lo, hi, iters);
+}
+
+double oracle_sigma_exact(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
+                          double mu, double lo, double hi, int iters) {
+    struct pairs_ctx c = {n, d, X, row_ptr, col_idx, mu};
+    return bisect_sigma(pairs_fn, &c, lo, hi, iters);
+}

@@ -258,6 +258,81 @@ def pin_wm_identity():
             assert close(d2, rd2, 1e-8)
 
 
+# ----------------------------------------------------------------------------------------
+# slope optimisation (Sec. III-F)
+# ----------------------------------------------------------------------------------------
+
+def _sigma_case():
+    """Three blocks placed around three centres: edges are mostly short, non-edges long, so
+    Eq. 2 has an interior minimum over sigma (for an unstructured embedding it decreases all
+    the way to 1 bit per pair as sigma grows)."""
+    g = synth.sbm(3, 20, 0.5, 0.02, seed=41, permute=False)
+    rng = np.random.default_rng(42)
+    centres = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 3.0]])
+    X = centres[np.repeat(np.arange(3), 20)] + 0.6 * rng.standard_normal((60, 2))
+    return g, X
+
+
+def pin_histogram_counts():
+    """Counts add up to N pairs and m edges; at d = 1 every pair's bin equals a brute force in
+    numpy single precision (one rounding of the product, as the fused multiply-add gives)."""
+    g = synth.erdos_renyi(50, 5.0, seed=43)
+    X = synth.init_embedding(50, 1, seed=44)
+    r2_max = float(4 * np.max((X - X[0]) ** 2) * 1.001)
+    nb = 257
+    ha, he = oracle.histogram(X, g.row_ptr, g.col_idx, nb, r2_max)
+    assert int(ha.sum()) == 50 * 49 // 2 and int(he.sum()) == g.m
+    inv_w = np.float32(nb / r2_max)
+    bha = np.zeros(nb, np.int64)
+    bhe = np.zeros(nb, np.int64)
+    edges = {(int(i), int(j)) for i, j in g.edges_upper()}
+    x = X[:, 0].astype(np.float32)
+    for i in range(50):
+        for j in range(i + 1, 50):
+            df = np.float32(x[i] - x[j])
+            r2 = np.float32(df * df)
+            b = int(min(np.float32(r2 * inv_w), np.float32(nb - 1)))
+            bha[b] += 1
+            if (i, j) in edges:
+                bhe[b] += 1
+    assert np.array_equal(bha, ha.astype(np.int64)) and np.array_equal(bhe, he.astype(np.int64))
+    X3 = synth.init_embedding(50, 3, seed=45)
+    ha3, he3 = oracle.histogram(X3, g.row_ptr, g.col_idx, 64, float(4 * np.max(np.sum((X3 - X3[0]) ** 2, 1)) * 1.001))
+    assert int(ha3.sum()) == 50 * 49 // 2 and int(he3.sum()) == g.m
+
+
+def pin_sigma_minimises_loss():
+    """The exact slope is a minimum of Eq. 2 over sigma (the pinned loss), with a vanishing
+    central difference, and it scales with the embedding: sigma*(cX; c mu) = c sigma*(X; mu)."""
+    g, X = _sigma_case()
+    s = oracle.sigma_exact(X, g.row_ptr, g.col_idx, MU)
+    assert 1e-2 < s < 1e2
+
+    def DL(sig):
+        return oracle.loss_grad(X, g.row_ptr, g.col_idx, MU, sig, want_grad=False)["loss"]
+
+    base = DL(s)
+    for f in (0.99, 0.999, 1.001, 1.01):
+        assert DL(s * f) > base
+    h = 1e-4
+    slope_scale = abs(DL(s * 1.1) - DL(s * 0.9)) / (0.2 * s)
+    assert abs(DL(s * (1 + h)) - DL(s * (1 - h))) / (2 * h * s) <= 1e-4 * max(slope_scale, 1.0)
+    s3 = oracle.sigma_exact(3.0 * X, g.row_ptr, g.col_idx, 3.0 * MU)
+    assert abs(s3 / s - 3.0) <= 1e-9
+
+
+def pin_sigma_histogram_converges():
+    """The histogram bisection approaches the exact slope as the bins get finer."""
+    g, X = _sigma_case()
+    s = oracle.sigma_exact(X, g.row_ptr, g.col_idx, MU)
+    r2_max = float(4 * np.max(np.sum((X - X[0]) ** 2, 1)) * 1.001)
+    errs = []
+    for nb in (256, 16384):
+        ha, he = oracle.histogram(X, g.row_ptr, g.col_idx, nb, r2_max)
+        errs.append(abs(oracle.sigma_from_histogram(ha, he, r2_max, MU) / s - 1))
+    assert errs[1] < 2e-5 and errs[1] < errs[0]
+
+
 ALL_PINS = [
     pin_pair_vs_mpmath,
     pin_pair_vs_scipy,
@@ -269,4 +344,7 @@ ALL_PINS = [
     pin_invariances,
     pin_edge_hits_and_rows,
     pin_wm_identity,
+    pin_histogram_counts,
+    pin_sigma_minimises_loss,
+    pin_sigma_histogram_converges,
 ]

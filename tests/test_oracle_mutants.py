@@ -26,6 +26,12 @@ MUTANTS = {
     "tail_log_term": ("- log(-t) - ORACLE_LOG_SQRT_2PI", "+ log(-t) - ORACLE_LOG_SQRT_2PI"),
     "second_derivative_sign": ("(tau * R + R * R)", "(tau * R - R * R)"),
     "distance_not_squared": ("r2 += t * t;", "r2 += fabs(t);"),
+    "hist_edge_tau_sign": ("if (e > 0) F += e * (-t) * mills_inv(-t);", "if (e > 0) F += e * t * mills_inv(t);"),
+    "hist_bin_lower_edge": ("double delta = sqrt((b + 0.5) * r2_max / nbins);",
+                            "double delta = sqrt(b * r2_max / nbins);"),
+    "hist_edge_row_flag": ("if (flag[j]) he[b] += 1;", "if (flag[i]) he[b] += 1;"),
+    "pairs_edge_sign": ("double a = flag[j] ? -1.0 : 1.0;", "double a = flag[j] ? 1.0 : -1.0;"),
+    "bisection_direction": ("if (Fn(s, ctx) < 0.0) lo = s; else hi = s;", "if (Fn(s, ctx) < 0.0) hi = s; else lo = s;"),
 }
 
 
