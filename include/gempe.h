@@ -185,6 +185,47 @@ gempe_status gempe_embed_wm(gempe_graph g, int32_t d, float *X, int32_t iters, d
                             size_t ws_bytes, const gempe_params *p, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Slope optimisation (Sec. III-F).  mu stays fixed; sigma is chosen where d DL / d sigma = 0,
+ * i.e. where F(sigma) = sum_{i<j} tau_ij R(tau_ij) vanishes (d tau / d sigma = -tau / sigma),
+ * located by bisection on histograms of the pair distances kept separately for edges and
+ * non-edges.  Histogram layout: nbins bins uniform in the squared distance on [0, r2_max);
+ * a pair goes to bin floor(min(r2 * inv_w, nbins - 1)), inv_w = nbins / r2_max in single
+ * precision, r2 the single-precision squared distance summed over the coordinates in order
+ * with fused multiply-adds; a bin stands for the distance sqrt((b + 1/2) r2_max / nbins).
+ * ------------------------------------------------------------------------------------ */
+
+/* Workspace of gempe_distance_histogram (and the extra part gempe_embed_wm_sigma needs
+ * beyond gempe_workspace_bytes); 0 on invalid arguments.  2 <= nbins <= 16384. [host] */
+size_t gempe_histogram_workspace_bytes(gempe_graph g, int32_t d, int32_t nbins);
+
+/* Counts of all unordered pairs (hist_all) and of the edges (hist_edge) per bin, uint64[nbins]
+ * each, device.  Exact integer counts (deterministic).  Asynchronous. */
+gempe_status gempe_distance_histogram(gempe_graph g, int32_t d, const float *X, int32_t nbins, float r2_max,
+                                      uint64_t *hist_all, uint64_t *hist_edge, void *ws, size_t ws_bytes,
+                                      hipStream_t stream);
+
+/* *r2_max [host] = (squared diagonal of the coordinates' bounding box)(1 + 1e-5), an upper
+ * bound of every pair's squared distance.  Synchronous; GEMPE_ERR_NUMERIC for non-finite
+ * coordinates; ws >= 1024 bytes. */
+gempe_status gempe_r2_bound(gempe_graph g, int32_t d, const float *X, float *r2_max, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* Bisection (200 geometric halvings of [sigma_lo, sigma_hi]) of F on the histograms
+ * (host arrays); returns a bracket end when F does not change sign in it (the minimum of
+ * Eq. 2 over that interval lies on its boundary). [host] */
+gempe_status gempe_sigma_fit(int32_t nbins, float r2_max, const uint64_t *hist_all, const uint64_t *hist_edge,
+                             double mu, double sigma_lo, double sigma_hi, double *sigma);
+
+/* Weighted majorization with the slope refitted after every sigma_every steps (the loop of
+ * Fig. algo: WM step, then histograms and sigma): *sigma [host] holds the initial slope and
+ * receives the last one; loss_hist[k] = DL(X_k) at the slope step k used.  Workspace:
+ * gempe_workspace_bytes + gempe_histogram_workspace_bytes.  Synchronises at every refit and
+ * at the end (GEMPE_ERR_NUMERIC if a non-finite loss appeared). */
+gempe_status gempe_embed_wm_sigma(gempe_graph g, int32_t d, float *X, int32_t iters, int32_t sigma_every,
+                                  int32_t nbins, double *sigma, double *loss_hist, void *ws, size_t ws_bytes,
+                                  const gempe_params *p, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Serving: a request loop that runs many embedding jobs (each one gempe_embed-style
  * gradient-descent run on its own graph) on one GPU with continuous batching.
  *

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -243,5 +244,137 @@ extern "C" gempe_status gempe_embed_wm(gempe_graph g, int32_t d, float *X, int32
     GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
     GEMPE_HIP_TRY(hipStreamSynchronize(stream));
     if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_wm: non-finite loss");
+    return GEMPE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Slope optimisation (Sec. III-F)
+// ------------------------------------------------------------------------------------
+
+namespace {
+constexpr int kSigmaIters = 200;
+constexpr double kSigmaLo = 1e-3, kSigmaHi = 1e3;
+
+gempe_status check_nbins(int32_t nbins, const char *who) {
+    if (nbins < 2 || nbins > 16384)
+        return gempe_fail(GEMPE_ERR_ARG, std::string(who) + ": nbins must be in [2, 16384]");
+    return GEMPE_OK;
+}
+
+size_t hist_ws_bytes(const gempe_graph_s *g, int d, int nbins) {
+    // partial histograms, then the two device histograms and the r2 word
+    return ((gempe_hist_partial_bytes(g->n, d, nbins) + 255) & ~size_t(255)) + 2 * 8 * (size_t)nbins + 1024;
+}
+}  // namespace
+
+extern "C" size_t gempe_histogram_workspace_bytes(gempe_graph g, int32_t d, int32_t nbins) {
+    if (!g || d < 1 || d > 128 || nbins < 2 || nbins > 16384) return 0;
+    return hist_ws_bytes(g, d, nbins);
+}
+
+extern "C" gempe_status gempe_distance_histogram(gempe_graph g, int32_t d, const float *X, int32_t nbins,
+                                                 float r2_max, uint64_t *hist_all, uint64_t *hist_edge, void *ws,
+                                                 size_t ws_bytes, hipStream_t stream) {
+    if (!g) return gempe_fail(GEMPE_ERR_ARG, "distance_histogram: null graph handle");
+    if (d < 1 || d > 128) return gempe_fail(GEMPE_ERR_ARG, "distance_histogram: d must be in [1, 128]");
+    gempe_status st = check_nbins(nbins, "distance_histogram");
+    if (st != GEMPE_OK) return st;
+    if (!X || !hist_all || !hist_edge || !ws) return gempe_fail(GEMPE_ERR_ARG, "distance_histogram: null pointer");
+    if (!(std::isfinite(r2_max) && r2_max > 0.0f))
+        return gempe_fail(GEMPE_ERR_ARG, "distance_histogram: r2_max must be finite and > 0");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return gempe_fail(GEMPE_ERR_ARG, "distance_histogram: workspace must be 256-byte aligned");
+    if (ws_bytes < gempe_hist_partial_bytes(g->n, d, nbins))
+        return gempe_fail(GEMPE_ERR_NOMEM, "distance_histogram: workspace too small");
+    GEMPE_HIP_TRY(gempe_launch_histogram(g, d, X, nbins, r2_max, reinterpret_cast<unsigned long long *>(hist_all),
+                                         reinterpret_cast<unsigned long long *>(hist_edge), ws, stream));
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_r2_bound(gempe_graph g, int32_t d, const float *X, float *r2_max, void *ws,
+                                       size_t ws_bytes, hipStream_t stream) {
+    if (!g || !X || !r2_max || !ws) return gempe_fail(GEMPE_ERR_ARG, "r2_bound: null argument");
+    if (d < 1 || d > 128) return gempe_fail(GEMPE_ERR_ARG, "r2_bound: d must be in [1, 128]");
+    if (ws_bytes < 2 * 4 * 128) return gempe_fail(GEMPE_ERR_NOMEM, "r2_bound: workspace too small");
+    int *box = static_cast<int *>(ws);
+    GEMPE_HIP_TRY(gempe_launch_box(g, d, X, box, stream));
+    int codes[256];
+    GEMPE_HIP_TRY(hipMemcpyAsync(codes, box, sizeof(int) * 2 * d, hipMemcpyDeviceToHost, stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+    // every pair lies inside the bounding box, so its squared distance is below the squared
+    // diagonal; the margin covers the single-precision rounding of the pairs' sums
+    double diag2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double lo = gempe_box_code_to_float(codes[k]), hi = gempe_box_code_to_float(codes[d + k]);
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return gempe_fail(GEMPE_ERR_NUMERIC, "r2_bound: non-finite coordinates");
+        diag2 += (hi - lo) * (hi - lo);
+    }
+    *r2_max = (float)(diag2 * (1.0 + 1e-5) + 1e-30);
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_sigma_fit(int32_t nbins, float r2_max, const uint64_t *hist_all,
+                                        const uint64_t *hist_edge, double mu, double sigma_lo, double sigma_hi,
+                                        double *sigma) {
+    gempe_status st = check_nbins(nbins, "sigma_fit");
+    if (st != GEMPE_OK) return st;
+    if (!hist_all || !hist_edge || !sigma) return gempe_fail(GEMPE_ERR_ARG, "sigma_fit: null pointer");
+    if (!(std::isfinite(r2_max) && r2_max > 0.0f) || !std::isfinite(mu))
+        return gempe_fail(GEMPE_ERR_ARG, "sigma_fit: r2_max and mu must be finite, r2_max > 0");
+    if (!(sigma_lo > 0.0 && sigma_hi > sigma_lo && std::isfinite(sigma_hi)))
+        return gempe_fail(GEMPE_ERR_ARG, "sigma_fit: need 0 < sigma_lo < sigma_hi < inf");
+    for (int b = 0; b < nbins; ++b)
+        if (hist_edge[b] > hist_all[b]) return gempe_fail(GEMPE_ERR_ARG, "sigma_fit: an edge count exceeds its bin");
+    *sigma = gempe_bisect_sigma(nbins, (double)r2_max, hist_all, hist_edge, mu, sigma_lo, sigma_hi, kSigmaIters);
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_embed_wm_sigma(gempe_graph g, int32_t d, float *X, int32_t iters,
+                                             int32_t sigma_every, int32_t nbins, double *sigma, double *loss_hist,
+                                             void *ws, size_t ws_bytes, const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "embed_wm_sigma");
+    if (st != GEMPE_OK) return st;
+    if (!X || !sigma) return gempe_fail(GEMPE_ERR_ARG, "embed_wm_sigma: X and sigma are required");
+    if (iters < 0 || sigma_every < 1) return gempe_fail(GEMPE_ERR_ARG, "embed_wm_sigma: iters >= 0, sigma_every >= 1");
+    if ((st = check_nbins(nbins, "embed_wm_sigma")) != GEMPE_OK) return st;
+    if (!(std::isfinite(*sigma) && *sigma > 0.0))
+        return gempe_fail(GEMPE_ERR_ARG, "embed_wm_sigma: the initial sigma must be finite and > 0");
+    gempe_params q = *p;
+    q.sigma = *sigma;
+    SweepPlan plan = gempe_make_plan(g, d, q.precision == GEMPE_BF16_GRAM);
+    WsLayout L = gempe_ws_layout(g, d, plan);
+    WsLayout Lh = L;
+    Lh.total = L.total + hist_ws_bytes(g, d, nbins);  // the histogram region follows the layout
+    if ((st = check_ws(g, d, ws, ws_bytes, Lh, "embed_wm_sigma")) != GEMPE_OK) return st;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    unsigned char *hw = w + L.total;  // histogram region
+    const size_t part = (gempe_hist_partial_bytes(g->n, d, nbins) + 255) & ~size_t(255);
+    uint64_t *dev_all = reinterpret_cast<uint64_t *>(hw + part);
+    uint64_t *dev_edge = dev_all + nbins;
+    void *word = dev_edge + nbins;
+    unsigned *status_ws = reinterpret_cast<unsigned *>(w + L.counters + 8);
+    std::vector<uint64_t> h_all(nbins), h_edge(nbins);
+    for (int k = 0; k <= iters; ++k) {
+        if (k == iters && !loss_hist) break;
+        GEMPE_HIP_TRY(gempe_enqueue_embed_steps(g, d, plan, L, w, X, iters, 1.0f, loss_hist, &q, stream, k, k + 1,
+                                                true));
+        if (k < iters && (k + 1) % sigma_every == 0) {
+            // histograms of the new coordinates, then the slope where d DL / d sigma = 0
+            float r2_max = 0.0f;
+            if ((st = gempe_r2_bound(g, d, X, &r2_max, word, 1024, stream)) != GEMPE_OK) return st;
+            GEMPE_HIP_TRY(gempe_launch_histogram(g, d, X, nbins, r2_max, reinterpret_cast<unsigned long long *>(dev_all),
+                                                 reinterpret_cast<unsigned long long *>(dev_edge), hw, stream));
+            GEMPE_HIP_TRY(hipMemcpyAsync(h_all.data(), dev_all, 8 * (size_t)nbins, hipMemcpyDeviceToHost, stream));
+            GEMPE_HIP_TRY(hipMemcpyAsync(h_edge.data(), dev_edge, 8 * (size_t)nbins, hipMemcpyDeviceToHost, stream));
+            GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+            q.sigma = gempe_bisect_sigma(nbins, (double)r2_max, h_all.data(), h_edge.data(), q.mu, kSigmaLo, kSigmaHi,
+                                         kSigmaIters);
+        }
+    }
+    *sigma = q.sigma;
+    unsigned host_status = 0;
+    GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, status_ws, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+    if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_wm_sigma: non-finite loss");
     return GEMPE_OK;
 }

@@ -186,3 +186,13 @@ hipError_t gempe_enqueue_embed_steps(const gempe_graph_s *g, int d, const SweepP
                                      unsigned char *w, float *X, int iters, float eta, double *loss_hist,
                                      const gempe_params *p, hipStream_t stream, int k_begin, int k_end,
                                      bool wm = false);
+
+// Distance histograms and the slope bisection (hist.hip).
+size_t gempe_hist_partial_bytes(int n, int d, int nbins);
+hipError_t gempe_launch_histogram(const gempe_graph_s *g, int d, const float *X, int nbins, float r2_max,
+                                  unsigned long long *hist_all, unsigned long long *hist_edge, void *scratch,
+                                  hipStream_t s);
+hipError_t gempe_launch_box(const gempe_graph_s *g, int d, const float *X, int *box, hipStream_t s);
+float gempe_box_code_to_float(int c);
+double gempe_bisect_sigma(int nbins, double r2_max, const uint64_t *all, const uint64_t *edge, double mu,
+                          double lo, double hi, int iters);

@@ -1,0 +1,66 @@
+// Device helpers shared by the sweeps and the distance histogram: the upper-triangle tile
+// order, the XCD-aware workgroup mapping, the DPP wave rotation of the Latin-square
+// schedule, and the squared distance accumulated coordinate by coordinate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gempe {
+
+constexpr int kXcd = 8;  // MI355X: workgroups are dealt round-robin over 8 XCDs
+
+// Upper-triangle tile t (row-major over I <= J < nt) -> (I, J).
+__device__ inline void tile_of(long long t, int nt, int &I, int &J) {
+    double b = 2.0 * nt + 1.0;
+    long long i = (long long)floor((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > nt - 1) i = nt - 1;
+    auto start = [nt](long long ii) { return ii * nt - ii * (ii - 1) / 2; };
+    while (i > 0 && start(i) > t) --i;
+    while (i + 1 < nt && start(i + 1) <= t) ++i;
+    I = (int)i;
+    J = (int)(i + (t - start(i)));
+}
+
+// Workgroup b -> tile index such that the workgroups one XCD receives (b = x, x+8, ...)
+// take consecutive tiles (same row strip: x_I stays in that XCD's L2).
+__device__ inline long long xcd_item(long long b, long long per_xcd) {
+    return (b % kXcd) * per_xcd + b / kXcd;
+}
+
+__device__ __forceinline__ float rot1(float v) {
+    // DPP wave rotation by one lane, in place (all rows and banks enabled)
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x134, 0xF, 0xF, false));
+}
+
+// The same rotation written so that the compiler folds it into the consuming add
+// (v_add_f32_dpp): every source lane is valid for a wave rotation.
+__device__ __forceinline__ float rot1_fold(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xF, 0xF, true));
+}
+
+// +1 if the rotation brings lane l+1's value to lane l, else -1.
+__device__ __forceinline__ int rot_dir(int lane) {
+    return (__float_as_int(rot1(__int_as_float(lane))) == ((lane + 1) & 63)) ? 1 : -1;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Squared distance, coordinates in order with fused multiply-adds (padding coordinates are
+// zero on both sides and add exactly 0).
+template <int D>
+__device__ __forceinline__ float sqdist(const float (&a)[D], const float (&b)[D], float (&diff)[D]) {
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        diff[k] = a[k] - b[k];
+        r2 = __builtin_fmaf(diff[k], diff[k], r2);
+    }
+    return r2;
+}
+
+}  // namespace gempe

@@ -45,6 +45,11 @@ ABI_SYMBOLS = (
     "gempe_wm_terms",
     "gempe_wm_step",
     "gempe_embed_wm",
+    "gempe_histogram_workspace_bytes",
+    "gempe_distance_histogram",
+    "gempe_r2_bound",
+    "gempe_sigma_fit",
+    "gempe_embed_wm_sigma",
     "gempe_job_footprint",
     "gempe_server_create",
     "gempe_server_submit",
@@ -165,6 +170,19 @@ def load(path: str | None = None):
     lib.gempe_wm_step.restype = st
     lib.gempe_embed_wm.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, P, vp]
     lib.gempe_embed_wm.restype = st
+    lib.gempe_histogram_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    lib.gempe_histogram_workspace_bytes.restype = ctypes.c_size_t
+    lib.gempe_distance_histogram.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp,
+                                             ctypes.c_size_t, vp]
+    lib.gempe_distance_histogram.restype = st
+    lib.gempe_r2_bound.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_float), vp, ctypes.c_size_t, vp]
+    lib.gempe_r2_bound.restype = st
+    lib.gempe_sigma_fit.argtypes = [ctypes.c_int32, ctypes.c_float, vp, vp, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+    lib.gempe_sigma_fit.restype = st
+    lib.gempe_embed_wm_sigma.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.c_size_t, P, vp]
+    lib.gempe_embed_wm_sigma.restype = st
     lib.gempe_job_footprint.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
     lib.gempe_job_footprint.restype = ctypes.c_size_t
     lib.gempe_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -377,6 +395,67 @@ def embed_wm(g: Graph, X, iters: int, ws=None, params=None, loss_hist=None, stre
     _check(load().gempe_embed_wm(g.handle, int(d), _ptr(X), int(iters), _ptr(loss_hist), _ptr(ws),
                                  int(ws.numel()), ctypes.byref(p), _stream(stream)))
     return X
+
+
+# ------------------------------------------------------------------------------------
+# slope optimisation
+# ------------------------------------------------------------------------------------
+
+def histogram_workspace(g: Graph, d: int, nbins: int):
+    torch = _torch()
+    nbytes = int(load().gempe_histogram_workspace_bytes(g.handle, int(d), int(nbins)))
+    if nbytes == 0:
+        raise GempeError(GEMPE_ERR_ARG, "histogram_workspace_bytes: invalid arguments")
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def r2_bound(g: Graph, X, ws=None, stream=None) -> float:
+    torch = _torch()
+    n, d = X.shape
+    if ws is None:
+        ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_float()
+    _check(load().gempe_r2_bound(g.handle, int(d), _ptr(X), ctypes.byref(out), _ptr(ws), int(ws.numel()),
+                                 _stream(stream)))
+    return float(out.value)
+
+
+def distance_histogram(g: Graph, X, nbins: int, r2_max: float, ws=None, stream=None):
+    """(hist_all, hist_edge) as int64 CUDA tensors (the uint64 counts, which fit)."""
+    torch = _torch()
+    n, d = X.shape
+    if ws is None:
+        ws = histogram_workspace(g, d, nbins)
+    ha = torch.empty(nbins, dtype=torch.int64, device="cuda")
+    he = torch.empty(nbins, dtype=torch.int64, device="cuda")
+    _check(load().gempe_distance_histogram(g.handle, int(d), _ptr(X), int(nbins), float(r2_max), _ptr(ha), _ptr(he),
+                                           _ptr(ws), int(ws.numel()), _stream(stream)))
+    return ha, he
+
+
+def sigma_fit(hist_all, hist_edge, r2_max: float, mu: float = 1.5, sigma_lo: float = 1e-3,
+              sigma_hi: float = 1e3) -> float:
+    ha = np.ascontiguousarray(hist_all, dtype=np.uint64)
+    he = np.ascontiguousarray(hist_edge, dtype=np.uint64)
+    out = ctypes.c_double()
+    _check(load().gempe_sigma_fit(int(ha.size), float(r2_max), ha.ctypes.data, he.ctypes.data, float(mu),
+                                  float(sigma_lo), float(sigma_hi), ctypes.byref(out)))
+    return float(out.value)
+
+
+def embed_wm_sigma(g: Graph, X, iters: int, sigma: float, sigma_every: int = 1, nbins: int = 4096, params=None,
+                   loss_hist=None, stream=None) -> float:
+    """Weighted majorization with the slope refitted every sigma_every steps; returns the last slope."""
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    nbytes = workspace_bytes(g, d, p) + int(load().gempe_histogram_workspace_bytes(g.handle, int(d), int(nbins)))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = ctypes.c_double(float(sigma))
+    _check(load().gempe_embed_wm_sigma(g.handle, int(d), _ptr(X), int(iters), int(sigma_every), int(nbins),
+                                       ctypes.byref(s), _ptr(loss_hist), _ptr(ws), int(ws.numel()), ctypes.byref(p),
+                                       _stream(stream)))
+    return float(s.value)
 
 
 # ------------------------------------------------------------------------------------

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "gempe.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(gempe_[a-z_]+)\s*\(", text)
+    names = re.findall(r"\b(gempe_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))
 
 
