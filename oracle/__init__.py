@@ -70,6 +70,11 @@ def _bind(path: str):
     lib.oracle_sigma_exact.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.oracle_sigma_exact.restype = ctypes.c_double
+    lib.oracle_sample_pairs.argtypes = [ctypes.c_int, i64p, i32p, ctypes.c_uint64, ctypes.c_int, i32p]
+    lib.oracle_sample_pairs.restype = None
+    lib.oracle_sampled_step.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_uint64, ctypes.c_int, dp, dp, i32p]
+    lib.oracle_sampled_step.restype = None
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     return lib
@@ -256,3 +261,32 @@ def sigma_exact(X, row_ptr, col_idx, mu: float = 1.5, lo=SIGMA_LO, hi=SIGMA_HI, 
     rp, ci = _graph_arrays(row_ptr, col_idx)
     return float(lib.oracle_sigma_exact(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64),
                                         _ptr(ci, ctypes.c_int32), float(mu), float(lo), float(hi), int(iters)))
+
+
+# ------------------------------------------------------------------------------------
+# negative sampling (Sec. III-C)
+# ------------------------------------------------------------------------------------
+
+def sample_pairs(row_ptr, col_idx, n: int, seed: int, max_tries: int = 32):
+    """int32[2 nnz]: the sampled non-neighbours of both ends of every entry with i < j."""
+    lib = _load()
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    out = np.empty(2 * max(int(rp[-1]), 1), dtype=np.int32)
+    lib.oracle_sample_pairs(int(n), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32), ctypes.c_uint64(seed),
+                            int(max_tries), _ptr(out, ctypes.c_int32))
+    return out[:2 * int(rp[-1])]
+
+
+def sampled_step(X, row_ptr, col_idx, seed: int, max_tries: int = 32, mu: float = 1.5, sigma: float = 1.0):
+    """One negative-sampled weighted-majorization step: (X_new, dl over the pairs used, samples)."""
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    Xn = np.empty_like(Xd)
+    loss = ctypes.c_double()
+    smp = np.empty(2 * max(int(rp[-1]), 1), dtype=np.int32)
+    lib.oracle_sampled_step(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
+                            float(mu), float(sigma), ctypes.c_uint64(seed), int(max_tries),
+                            _ptr(Xn, ctypes.c_double), ctypes.byref(loss), _ptr(smp, ctypes.c_int32))
+    return Xn, loss.value, smp[:2 * int(rp[-1])]

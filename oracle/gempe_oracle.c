@@ -346,3 +346,124 @@ double oracle_sigma_exact(int n, int d, const double *X, const int64_t *row_ptr,
     struct pairs_ctx c = {n, d, X, row_ptr, col_idx, mu};
     return bisect_sigma(pairs_fn, &c, lo, hi, iters);
 }
+
+/*
+ * Negative sampling (Sec. III-C, Fig. nonedges, Fig. algo).  Every edge (i, j), i < j, takes
+ * part with its own parabola, and with two sampled non-edges: a vertex g with (g, i) not in E
+ * for i, and h with (h, j) not in E for j.  One step is Eq. 5 over that multiset of pairs,
+ * i.e. x_v <- y_v / z_v with y and z summed over the pairs that contain v; a vertex in no
+ * pair keeps its coordinates.
+ *
+ * Random draws.  The paper's generator is the 32-bit LCG s <- 1103515245 s + 1 (mod 2^32),
+ * mapped to a vertex by taking the low 23 bits of s as the mantissa of a float f in [1, 2)
+ * and rounding f n - n.  Readings: the float arithmetic is single precision, multiply then
+ * subtract; the rounding is floor (round-to-nearest can give n); a draw equal to the vertex
+ * itself, outside [0, n), or adjacent to it is rejected and the generator steps again, at
+ * most max_tries draws in all (then the sample is dropped: a vertex adjacent to every other
+ * has no non-edge).  Each sample owns its generator: the state starts from the upper 32 bits
+ * of SplitMix64 (Steele, Lea and Flood 2014) applied to seed + 2 e + side, e the CSR index
+ * of the entry (i, j) with i < j, side 0 for i and 1 for j, so the draws do not depend on
+ * how the work is divided.
+ * samples: int32[2 nnz]; for the entry e with i < j, samples[2e] = g, samples[2e + 1] = h
+ * (-1 when dropped); entries with i > j hold -1.
+ */
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+/* Is (a, b) an edge: binary search in a's sorted CSR row. */
+static int is_edge(const int64_t *row_ptr, const int32_t *col_idx, int a, int b) {
+    int64_t lo = row_ptr[a], hi = row_ptr[a + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (col_idx[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    return lo < row_ptr[a + 1] && col_idx[lo] == b;
+}
+
+static int draw_non_neighbour(int v, int n, uint32_t state, int max_tries, const int64_t *row_ptr,
+                              const int32_t *col_idx) {
+    const float nf = (float)n;
+    for (int t = 0; t < max_tries; ++t) {
+        state = 1103515245u * state + 1u;
+        uint32_t bits = 0x3f800000u | (state & 0x7fffffu);
+        float f;
+        memcpy(&f, &bits, sizeof(f));
+        volatile float prod = f * nf;  /* separate rounding of the product and the difference */
+        float u = prod - nf;
+        int c = (int)floorf(u);
+        if (c < 0 || c >= n || c == v) continue;
+        if (is_edge(row_ptr, col_idx, v, c)) continue;
+        return c;
+    }
+    return -1;
+}
+
+void oracle_sample_pairs(int n, const int64_t *row_ptr, const int32_t *col_idx, uint64_t seed, int max_tries,
+                         int32_t *samples) {
+    int64_t nnz = row_ptr[n];
+    for (int i = 0; i < n; ++i) {
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int j = col_idx[e];
+            samples[2 * e] = samples[2 * e + 1] = -1;
+            if (i >= j) continue;
+            uint32_t s0 = (uint32_t)(splitmix64(seed + 2 * (uint64_t)e) >> 32);
+            uint32_t s1 = (uint32_t)(splitmix64(seed + 2 * (uint64_t)e + 1) >> 32);
+            samples[2 * e] = draw_non_neighbour(i, n, s0, max_tries, row_ptr, col_idx);
+            samples[2 * e + 1] = draw_non_neighbour(j, n, s1, max_tries, row_ptr, col_idx);
+        }
+    }
+    (void)nnz;
+}
+
+/* Adds one pair's parabola (Eq. 3-4) to y and z of both ends, and its dl to *loss. */
+static void add_pair(int d, const double *X, int a, int b, int edge, double mu, double sigma, double *Y,
+                     double *Z, double *loss) {
+    double r2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double diff = X[(size_t)a * d + k] - X[(size_t)b * d + k];
+        r2 += diff * diff;
+    }
+    double delta = sqrt(r2), dl, d1, d2;
+    oracle_pair(delta, edge, mu, sigma, &dl, &d1, &d2);
+    double w = 0.5 * d2;
+    double dij = delta - d1 / (2.0 * w);
+    double s = (delta > 0.0) ? dij / delta : 0.0;
+    for (int k = 0; k < d; ++k) {
+        double xa = X[(size_t)a * d + k], xb = X[(size_t)b * d + k];
+        Y[(size_t)a * d + k] += w * (xb + s * (xa - xb));
+        Y[(size_t)b * d + k] += w * (xa + s * (xb - xa));
+    }
+    Z[a] += w;
+    Z[b] += w;
+    *loss += dl;
+}
+
+/* One negative-sampled weighted-majorization step from X (FP64): X_new, the dl summed over
+ * the pairs used (edges and samples), and the samples drawn. */
+void oracle_sampled_step(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
+                         double mu, double sigma, uint64_t seed, int max_tries, double *X_new,
+                         double *loss_sampled, int32_t *samples) {
+    oracle_sample_pairs(n, row_ptr, col_idx, seed, max_tries, samples);
+    double *Y = (double *)calloc((size_t)n * d, sizeof(double));
+    double *Z = (double *)calloc((size_t)n, sizeof(double));
+    double loss = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int j = col_idx[e];
+            if (i >= j) continue;
+            add_pair(d, X, i, j, 1, mu, sigma, Y, Z, &loss);
+            if (samples[2 * e] >= 0) add_pair(d, X, i, samples[2 * e], 0, mu, sigma, Y, Z, &loss);
+            if (samples[2 * e + 1] >= 0) add_pair(d, X, j, samples[2 * e + 1], 0, mu, sigma, Y, Z, &loss);
+        }
+    }
+    for (int v = 0; v < n; ++v)
+        for (int k = 0; k < d; ++k)
+            X_new[(size_t)v * d + k] = (Z[v] > 0.0) ? Y[(size_t)v * d + k] / Z[v] : X[(size_t)v * d + k];
+    if (loss_sampled) *loss_sampled = loss;
+    free(Y);
+    free(Z);
+}

@@ -333,6 +333,98 @@ def pin_sigma_histogram_converges():
     assert errs[1] < 2e-5 and errs[1] < errs[0]
 
 
+# ----------------------------------------------------------------------------------------
+# negative sampling (Sec. III-C)
+# ----------------------------------------------------------------------------------------
+
+def _lcg_draw(state, n):
+    """One step of the paper's LCG and its float mapping, in numpy single precision."""
+    state = (1103515245 * state + 1) & 0xFFFFFFFF
+    f = np.array([0x3F800000 | (state & 0x7FFFFF)], dtype=np.uint32).view(np.float32)[0]
+    u = np.float32(np.float32(f * np.float32(n)) - np.float32(n))
+    return state, int(np.floor(u))
+
+
+def _splitmix_hi(x):
+    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return (x ^ (x >> 31)) >> 32
+
+
+def pin_sampler():
+    """Samples are non-neighbours drawn by the published LCG (replayed here in numpy), roughly
+    uniform over the non-neighbours; with no non-edge the sample is dropped."""
+    g = synth.erdos_renyi(120, 10.0, seed=51)
+    seed = 987654321
+    smp = oracle.sample_pairs(g.row_ptr, g.col_idx, g.n, seed, 32)
+    nbr = [set(g.col_idx[g.row_ptr[i]:g.row_ptr[i + 1]].tolist()) for i in range(g.n)]
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    for e in range(g.nnz):
+        i, j = int(rows[e]), int(g.col_idx[e])
+        if i > j:
+            assert smp[2 * e] == -1 and smp[2 * e + 1] == -1
+            continue
+        for side, v in ((0, i), (1, j)):
+            c = int(smp[2 * e + side])
+            assert 0 <= c < g.n and c != v and c not in nbr[v]
+            # replay: first accepted draw of this sample's own generator
+            st = _splitmix_hi(seed + 2 * e + side)
+            for _ in range(32):
+                st, cand = _lcg_draw(st, g.n)
+                if 0 <= cand < g.n and cand != v and cand not in nbr[v]:
+                    break
+            assert cand == c
+    # uniformity: many samples of one vertex's partner spread over its non-neighbours
+    star = synth.csr_from_edges(40, np.zeros(5, np.int64), np.arange(1, 6, dtype=np.int64))
+    counts = np.zeros(40)
+    for sd in range(400):
+        ss = oracle.sample_pairs(star.row_ptr, star.col_idx, 40, 1000 + sd, 32)
+        counts[ss[0::2][ss[0::2] >= 0]] += 1   # partners of vertex 0 (the hub)
+    allowed = np.arange(6, 40)
+    assert counts[:6].sum() == 0
+    expect = counts.sum() / allowed.size
+    assert np.max(np.abs(counts[allowed] - expect)) < 5 * np.sqrt(expect) + 5
+    k = 8
+    iu, ju = np.triu_indices(k, 1)
+    kg = synth.csr_from_edges(k, iu.astype(np.int64), ju.astype(np.int64))
+    assert np.all(oracle.sample_pairs(kg.row_ptr, kg.col_idx, k, 3, 16) == -1)
+
+
+def pin_sampled_step():
+    """The sampled step is Eq. 5 over the multiset {edges} + {sampled pairs}, written out here
+    with the pinned pair function; its loss is the dl summed over those pairs."""
+    g = synth.erdos_renyi(30, 4.0, seed=61)
+    X = np.random.default_rng(62).standard_normal((30, 2))
+    Xn, loss, smp = oracle.sampled_step(X, g.row_ptr, g.col_idx, 77, 32)
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    pairs = []
+    for e in range(g.nnz):
+        i, j = int(rows[e]), int(g.col_idx[e])
+        if i < j:
+            pairs.append((i, j, True))
+            if smp[2 * e] >= 0:
+                pairs.append((i, int(smp[2 * e]), False))
+            if smp[2 * e + 1] >= 0:
+                pairs.append((j, int(smp[2 * e + 1]), False))
+    Y = np.zeros_like(X)
+    Z = np.zeros(g.n)
+    L = 0.0
+    for a, b, edge in pairs:
+        delta = float(np.linalg.norm(X[a] - X[b]))
+        dl, d1, d2 = oracle.pair(delta, edge)
+        w = d2 / 2
+        s_ab = (delta - d1 / (2 * w)) / delta
+        Y[a] += w * (X[b] + s_ab * (X[a] - X[b]))
+        Y[b] += w * (X[a] + s_ab * (X[b] - X[a]))
+        Z[a] += w
+        Z[b] += w
+        L += dl
+    ref = np.where(Z[:, None] > 0, Y / np.where(Z > 0, Z, 1)[:, None], X)
+    assert np.allclose(Xn, ref, rtol=1e-12, atol=1e-12)
+    assert close(loss, L, 1e-12)
+
+
 ALL_PINS = [
     pin_pair_vs_mpmath,
     pin_pair_vs_scipy,
@@ -347,4 +439,6 @@ ALL_PINS = [
     pin_histogram_counts,
     pin_sigma_minimises_loss,
     pin_sigma_histogram_converges,
+    pin_sampler,
+    pin_sampled_step,
 ]

@@ -31,6 +31,11 @@ MUTANTS = {
                             "double delta = sqrt(b * r2_max / nbins);"),
     "hist_edge_row_flag": ("if (flag[j]) he[b] += 1;", "if (flag[i]) he[b] += 1;"),
     "pairs_edge_sign": ("double a = flag[j] ? -1.0 : 1.0;", "double a = flag[j] ? 1.0 : -1.0;"),
+    "lcg_increment": ("state = 1103515245u * state + 1u;", "state = 1103515245u * state;"),
+    "draw_rounds_to_nearest": ("int c = (int)floorf(u);", "int c = (int)lrintf(u);"),
+    "draw_keeps_neighbours": ("if (is_edge(row_ptr, col_idx, v, c)) continue;", ""),
+    "sample_side_swapped": ("samples[2 * e + 1] = draw_non_neighbour(j, n, s1,", "samples[2 * e + 1] = draw_non_neighbour(i, n, s1,"),
+    "sampled_edge_as_non_edge": ("add_pair(d, X, i, j, 1, mu, sigma, Y, Z, &loss);", "add_pair(d, X, i, j, 0, mu, sigma, Y, Z, &loss);"),
     "bisection_direction": ("if (Fn(s, ctx) < 0.0) lo = s; else hi = s;", "if (Fn(s, ctx) < 0.0) hi = s; else lo = s;"),
 }
 
