@@ -226,6 +226,38 @@ gempe_status gempe_embed_wm_sigma(gempe_graph g, int32_t d, float *X, int32_t it
                                   const gempe_params *p, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Negative sampling (Sec. III-C, Fig. algo): O(m) weighted-majorization steps.  Every edge
+ * (i, j) takes part with its parabola, plus two sampled non-edges (i, g) and (j, h); Eq. 5 is
+ * applied over that multiset of pairs (x_v <- x_v - g_v / (2 z_v) with g and z summed over the
+ * pairs containing v; a vertex in no pair keeps its coordinates).  Draws: the paper's 32-bit
+ * LCG s <- 1103515245 s + 1, one generator per sample seeded from the upper 32 bits of
+ * SplitMix64(seed + 2 e + side) (e the CSR index of the entry (i, j) with i < j, side 0 for
+ * g and 1 for h); the low 23 bits of s become the mantissa of f in [1, 2) and the candidate
+ * is floor(f n - n) in single precision (multiply, then subtract; floor where the paper
+ * rounds, so n itself cannot come out); a candidate equal to the vertex, outside [0, n) or
+ * adjacent to it (exact edge hash) is rejected and the generator steps again, at most
+ * max_tries (1..1024) draws, else the sample is dropped.  Pair arithmetic in FP32 (the
+ * precision field is ignored).
+ * ------------------------------------------------------------------------------------ */
+
+/* Workspace of gempe_sampled_step / gempe_embed_sampled (0 on invalid arguments). [host] */
+size_t gempe_sampled_workspace_bytes(gempe_graph g, int32_t d);
+
+/* One sampled step in place.  samples: int32[2 nnz] or NULL; for the entry e with i < j,
+ * samples[2e] = g and samples[2e + 1] = h (-1 when dropped), -1 for entries with i > j.
+ * loss_sampled (nullable): dl summed over the pairs used, FP64.  Asynchronous. */
+gempe_status gempe_sampled_step(gempe_graph g, int32_t d, float *X, uint64_t seed, int32_t max_tries,
+                                int32_t *samples, double *loss_sampled, void *ws, size_t ws_bytes,
+                                const gempe_params *p, hipStream_t stream);
+
+/* iters sampled steps, step k drawing with seed + 2 nnz k; loss_hist: float64[iters] or NULL
+ * (the sampled loss of each step's pairs at the X it started from).  Synchronises once at the
+ * end; GEMPE_ERR_NUMERIC if a non-finite loss appeared. */
+gempe_status gempe_embed_sampled(gempe_graph g, int32_t d, float *X, int32_t iters, uint64_t seed,
+                                 int32_t max_tries, double *loss_hist, void *ws, size_t ws_bytes,
+                                 const gempe_params *p, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Serving: a request loop that runs many embedding jobs (each one gempe_embed-style
  * gradient-descent run on its own graph) on one GPU with continuous batching.
  *

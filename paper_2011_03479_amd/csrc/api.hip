@@ -378,3 +378,58 @@ extern "C" gempe_status gempe_embed_wm_sigma(gempe_graph g, int32_t d, float *X,
     if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_wm_sigma: non-finite loss");
     return GEMPE_OK;
 }
+
+// ------------------------------------------------------------------------------------
+// Negative sampling (Sec. III-C)
+// ------------------------------------------------------------------------------------
+
+extern "C" size_t gempe_sampled_workspace_bytes(gempe_graph g, int32_t d) {
+    if (!g || d < 1 || d > 128) return 0;
+    return gempe_sampled_ws_bytes(g, d);
+}
+
+namespace {
+gempe_status check_sampled(gempe_graph g, int32_t d, float *X, int32_t max_tries, void *ws, size_t ws_bytes,
+                           const gempe_params *p, const char *who) {
+    gempe_status st = check_common(g, d, p, who);
+    if (st != GEMPE_OK) return st;
+    const std::string w(who);
+    if (!X) return gempe_fail(GEMPE_ERR_ARG, w + ": X is required");
+    if (max_tries < 1 || max_tries > 1024) return gempe_fail(GEMPE_ERR_ARG, w + ": max_tries must be in [1, 1024]");
+    if (!ws) return gempe_fail(GEMPE_ERR_ARG, w + ": null workspace");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return gempe_fail(GEMPE_ERR_ARG, w + ": workspace must be 256-byte aligned");
+    if (ws_bytes < gempe_sampled_ws_bytes(g, d)) return gempe_fail(GEMPE_ERR_NOMEM, w + ": workspace too small");
+    return GEMPE_OK;
+}
+}  // namespace
+
+extern "C" gempe_status gempe_sampled_step(gempe_graph g, int32_t d, float *X, uint64_t seed, int32_t max_tries,
+                                           int32_t *samples, double *loss_sampled, void *ws, size_t ws_bytes,
+                                           const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_sampled(g, d, X, max_tries, ws, ws_bytes, p, "sampled_step");
+    if (st != GEMPE_OK) return st;
+    GEMPE_HIP_TRY(gempe_launch_sampled_step(g, d, X, seed, max_tries, samples, loss_sampled, gempe_pair_params(p),
+                                            static_cast<unsigned char *>(ws), true, stream));
+    return GEMPE_OK;
+}
+
+extern "C" gempe_status gempe_embed_sampled(gempe_graph g, int32_t d, float *X, int32_t iters, uint64_t seed,
+                                            int32_t max_tries, double *loss_hist, void *ws, size_t ws_bytes,
+                                            const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_sampled(g, d, X, max_tries, ws, ws_bytes, p, "embed_sampled");
+    if (st != GEMPE_OK) return st;
+    if (iters < 0) return gempe_fail(GEMPE_ERR_ARG, "embed_sampled: iters must be >= 0");
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    const PairParamsHost pp = gempe_pair_params(p);
+    // step k draws from seed + 2 nnz k, so no (step, entry, side) counter repeats
+    for (int k = 0; k < iters; ++k)
+        GEMPE_HIP_TRY(gempe_launch_sampled_step(g, d, X, seed + 2ull * (uint64_t)g->nnz * (uint64_t)k, max_tries,
+                                                nullptr, loss_hist ? loss_hist + k : nullptr, pp, w, k == 0, stream));
+    unsigned host_status = 0;
+    GEMPE_HIP_TRY(hipMemcpyAsync(&host_status, gempe_sampled_status(g, d, w), sizeof(unsigned), hipMemcpyDeviceToHost,
+                                 stream));
+    GEMPE_HIP_TRY(hipStreamSynchronize(stream));
+    if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_sampled: non-finite loss");
+    return GEMPE_OK;
+}

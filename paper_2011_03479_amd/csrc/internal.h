@@ -196,3 +196,10 @@ hipError_t gempe_launch_box(const gempe_graph_s *g, int d, const float *X, int *
 float gempe_box_code_to_float(int c);
 double gempe_bisect_sigma(int nbins, double r2_max, const uint64_t *all, const uint64_t *edge, double mu,
                           double lo, double hi, int iters);
+
+// Negative-sampled weighted majorization (sampled.hip).
+size_t gempe_sampled_ws_bytes(const gempe_graph_s *g, int d);
+hipError_t gempe_launch_sampled_step(const gempe_graph_s *g, int d, float *X, unsigned long long seed, int max_tries,
+                                     int32_t *samples, double *loss, const PairParamsHost &pp, unsigned char *ws,
+                                     bool clear_status, hipStream_t s);
+unsigned *gempe_sampled_status(const gempe_graph_s *g, int d, unsigned char *ws);

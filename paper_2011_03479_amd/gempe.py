@@ -50,6 +50,9 @@ ABI_SYMBOLS = (
     "gempe_r2_bound",
     "gempe_sigma_fit",
     "gempe_embed_wm_sigma",
+    "gempe_sampled_workspace_bytes",
+    "gempe_sampled_step",
+    "gempe_embed_sampled",
     "gempe_job_footprint",
     "gempe_server_create",
     "gempe_server_submit",
@@ -183,6 +186,14 @@ def load(path: str | None = None):
     lib.gempe_embed_wm_sigma.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_double), vp, vp, ctypes.c_size_t, P, vp]
     lib.gempe_embed_wm_sigma.restype = st
+    lib.gempe_sampled_workspace_bytes.argtypes = [vp, ctypes.c_int32]
+    lib.gempe_sampled_workspace_bytes.restype = ctypes.c_size_t
+    lib.gempe_sampled_step.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_uint64, ctypes.c_int32, vp, vp, vp,
+                                       ctypes.c_size_t, P, vp]
+    lib.gempe_sampled_step.restype = st
+    lib.gempe_embed_sampled.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32, vp,
+                                        vp, ctypes.c_size_t, P, vp]
+    lib.gempe_embed_sampled.restype = st
     lib.gempe_job_footprint.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, P]
     lib.gempe_job_footprint.restype = ctypes.c_size_t
     lib.gempe_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(vp)]
@@ -456,6 +467,45 @@ def embed_wm_sigma(g: Graph, X, iters: int, sigma: float, sigma_every: int = 1, 
                                        ctypes.byref(s), _ptr(loss_hist), _ptr(ws), int(ws.numel()), ctypes.byref(p),
                                        _stream(stream)))
     return float(s.value)
+
+
+# ------------------------------------------------------------------------------------
+# negative sampling
+# ------------------------------------------------------------------------------------
+
+def sampled_workspace(g: Graph, d: int):
+    torch = _torch()
+    nbytes = int(load().gempe_sampled_workspace_bytes(g.handle, int(d)))
+    if nbytes == 0:
+        raise GempeError(GEMPE_ERR_ARG, "sampled_workspace_bytes: invalid arguments")
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def sampled_step(g: Graph, X, seed: int, max_tries: int = 32, ws=None, params=None, want_samples=False,
+                 stream=None):
+    """One negative-sampled WM step in place; returns (loss float64[1], samples int32[2 nnz] or None)."""
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = sampled_workspace(g, d)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    smp = torch.empty(max(2 * g.nnz, 1), dtype=torch.int32, device="cuda") if want_samples else None
+    _check(load().gempe_sampled_step(g.handle, int(d), _ptr(X), ctypes.c_uint64(int(seed)), int(max_tries), _ptr(smp),
+                                     _ptr(loss), _ptr(ws), int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return loss, (smp[:2 * g.nnz] if smp is not None else None)
+
+
+def embed_sampled(g: Graph, X, iters: int, seed: int, max_tries: int = 32, ws=None, params=None, loss_hist=None,
+                  stream=None):
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = sampled_workspace(g, d)
+    _check(load().gempe_embed_sampled(g.handle, int(d), _ptr(X), int(iters), ctypes.c_uint64(int(seed)),
+                                      int(max_tries), _ptr(loss_hist), _ptr(ws), int(ws.numel()), ctypes.byref(p),
+                                      _stream(stream)))
+    return X
 
 
 # ------------------------------------------------------------------------------------
