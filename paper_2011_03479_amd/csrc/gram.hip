@@ -25,6 +25,7 @@
 
 #include "internal.h"
 #include "pairfn.h"
+#include "tiles.h"
 
 namespace gempe {
 
@@ -236,7 +237,6 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
 // Thread t owns a contiguous range of 16-byte words; all-zero words (the common case) are
 // skipped with one compare.  The flag region is 16-byte aligned; bytes past `total` are
 // ignored.
-constexpr int kCompactThreads = 1024;
 
 __device__ __forceinline__ int flags_in_word(const uint4 &w, long long base, long long total) {
     int c = 0;
@@ -247,38 +247,196 @@ __device__ __forceinline__ int flags_in_word(const uint4 &w, long long base, lon
     return c;
 }
 
-__global__ __launch_bounds__(kCompactThreads) void k_compact(const unsigned char *__restrict__ flags,
-                                                             long long total, int *__restrict__ list,
-                                                             int *__restrict__ count) {
-    __shared__ int scan[kCompactThreads];
-    const int tid = threadIdx.x;
-    const uint4 *fw = reinterpret_cast<const uint4 *>(flags);
-    const long long nw = (total + 15) / 16;
-    const long long chunk = (nw + kCompactThreads - 1) / kCompactThreads;
-    const long long lo = std::min<long long>(nw, (long long)tid * chunk);
-    const long long hi = std::min<long long>(nw, lo + chunk);
+// Ordered compaction of the tile flags in three steps: per-chunk counts (one workgroup per
+// 4,096 flags), an exclusive scan of the chunk counts, per-chunk writes at the chunk's offset.
+// The list comes out in increasing tile order, so everything downstream is deterministic.
+constexpr int kChunkFlags = 4096;  // 256 threads x 16 flags (one uint4 each)
+
+__global__ __launch_bounds__(256) void k_flag_count(const unsigned char *__restrict__ flags, long long total,
+                                                    int *__restrict__ chunk_count) {
+    __shared__ int ws[4];
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;  // uint4 word index
     int c = 0;
-    for (long long q = lo; q < hi; ++q) {
-        uint4 w = fw[q];
-        if (w.x | w.y | w.z | w.w) c += flags_in_word(w, q * 16, total);
+    if (q * 16 < total) {
+        const uint4 w = reinterpret_cast<const uint4 *>(flags)[q];
+        if (w.x | w.y | w.z | w.w) c = flags_in_word(w, q * 16, total);
     }
-    scan[tid] = c;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
     __syncthreads();
-    for (int off = 1; off < kCompactThreads; off <<= 1) {  // inclusive Hillis-Steele scan
-        int v = tid >= off ? scan[tid - off] : 0;
+    if (threadIdx.x == 0) chunk_count[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(1024) void k_flag_scan(int *__restrict__ chunk_count, int chunks, int *__restrict__ count) {
+    __shared__ int sc[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < chunks; base += 1024) {
+        const int k = base + threadIdx.x;
+        const int v = k < chunks ? chunk_count[k] : 0;
+        sc[threadIdx.x] = v;
         __syncthreads();
-        scan[tid] += v;
+        for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+            const int u = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (k < chunks) chunk_count[k] = carry + sc[threadIdx.x] - v;  // exclusive offset
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sc[1023];
         __syncthreads();
     }
-    int pos = scan[tid] - c;
-    for (long long q = lo; q < hi; ++q) {
-        uint4 w = fw[q];
-        if (!(w.x | w.y | w.z | w.w)) continue;
-        const unsigned v[4] = {w.x, w.y, w.z, w.w};
-        for (int b = 0; b < 16; ++b)
-            if (q * 16 + b < total && ((v[b >> 2] >> (8 * (b & 3))) & 0xffu)) list[pos++] = (int)(q * 16 + b);
+    if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(256) void k_flag_write(const unsigned char *__restrict__ flags, long long total,
+                                                    const int *__restrict__ chunk_offset, int *__restrict__ list) {
+    __shared__ int sc[256];
+    const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+    uint4 w = {0u, 0u, 0u, 0u};
+    int c = 0;
+    if (q * 16 < total) {
+        w = reinterpret_cast<const uint4 *>(flags)[q];
+        if (w.x | w.y | w.z | w.w) c = flags_in_word(w, q * 16, total);
     }
-    if (tid == kCompactThreads - 1) *count = scan[tid];
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int u = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += u;
+        __syncthreads();
+    }
+    if (!c) return;
+    int pos = chunk_offset[blockIdx.x] + sc[threadIdx.x] - c;
+    const unsigned v[4] = {w.x, w.y, w.z, w.w};
+    for (int b = 0; b < 16; ++b)
+        if (q * 16 + b < total && ((v[b >> 2] >> (8 * (b & 3))) & 0xffu)) list[pos++] = (int)(q * 16 + b);
+}
+
+// ------------------------------------------------------------------------------------
+// The flagged tiles, one wave each in list order: the tile's BF16 Gram block is recomputed
+// on MFMA with the screen's operands, accumulation order and threshold, so the near test
+// picks exactly the pairs the screen saw.  A tile with at most kSparseNear near pairs is
+// finished here: each near pair, in a fixed order, is evaluated exactly in FP32 by the whole
+// wave (coordinates over lanes, the squared distance of the wide edge pass, so an edge among
+// them gets bit-identical non-edge values there) and the tile's loss goes to partial slot q.
+// A denser tile is marked for the exact tile pass (k_sweep_wide_list), which writes slot q.
+// ------------------------------------------------------------------------------------
+constexpr int kSparseNear = 128;
+constexpr int kNearTileGrid = 1024;
+
+template <int D, int EX>
+__global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ Xb, const float *__restrict__ X,
+                                                    const float *__restrict__ nrm,
+                                                    const float *__restrict__ smax128, int n, long long nb64,
+                                                    float theta0, const int *__restrict__ list,
+                                                    const int *__restrict__ count, gempe::PairParams P,
+                                                    float *__restrict__ G, float *__restrict__ extra,
+                                                    float *__restrict__ partials,
+                                                    unsigned char *__restrict__ dense) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lrow = lane & 31, lk = (lane >> 5) * 8;
+    const int cnt = *count;
+    for (int q = blockIdx.x * 4 + wave; q < cnt; q += gridDim.x * 4) {
+        int R64, C64;
+        gempe::tile_of(list[q], (int)nb64, R64, C64);
+        floatx16 acc[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < D / 16; ++kk) {
+            bf16x8 a0 = {}, a1 = {}, b0 = {}, b1 = {};
+            const int ra = R64 * 64 + lrow, rb = C64 * 64 + lrow;
+            if (ra < n) a0 = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)ra * D + kk * 16 + lk);
+            if (ra + 32 < n) a1 = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(ra + 32) * D + kk * 16 + lk);
+            if (rb < n) b0 = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)rb * D + kk * 16 + lk);
+            if (rb + 32 < n) b1 = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(rb + 32) * D + kk * 16 + lk);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        // the screen's threshold: strip of 128 rows I = R64 / 2, column block of 128
+        const float sI = smax128[R64 / 2];
+        float hb[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c = C64 * 64 + b * 32 + lrow;
+            const float th = theta0 + 0.0078125f * (sI + smax128[min(c, n - 1) / 128]);
+            hb[b] = c < n ? 0.5f * nrm[c] - 0.5f * th * th : INFINITY;
+        }
+        int c = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int ig = R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                const float ha = ig < n ? 0.5f * nrm[ig] : INFINITY;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int jg = C64 * 64 + b * 32 + lrow;
+                    const bool nr = ig < jg && acc[a][b][r] - ha > hb[b];
+                    c += nr ? 1 : 0;
+                    acc[a][b][r] = nr ? 1.0f : 0.0f;  // keep only the decision
+                }
+            }
+        int tot = c;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
+        float loss = 0.0f;
+        if (tot > kSparseNear) {
+            if (lane == 0) dense[q] = 1;
+        } else {
+            if (lane == 0) dense[q] = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        unsigned long long m = __ballot(acc[a][b][r] != 0.0f);
+                        while (m) {
+                            const int L = __builtin_ctzll(m);
+                            m &= m - 1;
+                            const int i = R64 * 64 + a * 32 + (r >> 2) * 8 + (L >> 5) * 4 + (r & 3);
+                            const int j = C64 * 64 + b * 32 + (L & 31);
+                            const float *xi = X + (size_t)i * D;
+                            const float *xj = X + (size_t)j * D;
+                            const float xi0 = lane < D ? xi[lane] : 0.0f;
+                            const float xi1 = lane + 64 < D ? xi[lane + 64] : 0.0f;
+                            const float df0 = xi0 - (lane < D ? xj[lane] : 0.0f);
+                            const float df1 = xi1 - (lane + 64 < D ? xj[lane + 64] : 0.0f);
+                            const float r2 = gempe::wave_sum(__builtin_fmaf(df1, df1, df0 * df0));
+                            float dl, cc, w = 0.0f;
+                            gempe::pair_eval_t<EX == 2>(r2, 1.0f, P, dl, cc, w);
+                            if (lane < D) {
+                                atomicAdd(&G[(size_t)i * D + lane], cc * df0);
+                                atomicAdd(&G[(size_t)j * D + lane], -(cc * df0));
+                            }
+                            if (lane + 64 < D) {
+                                atomicAdd(&G[(size_t)i * D + lane + 64], cc * df1);
+                                atomicAdd(&G[(size_t)j * D + lane + 64], -(cc * df1));
+                            }
+                            loss += dl;
+                            if (EX && lane == 0) {
+                                const float ex = (EX == 2) ? w : dl;
+                                atomicAdd(&extra[i], ex);
+                                atomicAdd(&extra[j], ex);
+                            }
+                        }
+                    }
+        }
+        if (lane == 0) partials[q] = loss;
+    }
 }
 
 }  // namespace gempe
@@ -287,7 +445,7 @@ using namespace gempe;
 
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
-                                    float theta0, hipStream_t s) {
+                                    float theta0, int *chunk, hipStream_t s) {
     const int n = g->n;
     hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d,
                        reinterpret_cast<__bf16 *>(Xb), nrm, snorm);
@@ -313,6 +471,47 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
     }
 #undef GEMPE_SCREEN
     const long long t64 = nb64 * (nb64 + 1) / 2;
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactThreads), 0, s, flags, t64, list, count);
+    const int chunks = (int)((t64 + kChunkFlags - 1) / kChunkFlags);
+    hipLaunchKernelGGL(k_flag_count, dim3(chunks), dim3(256), 0, s, flags, t64, chunk);
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, chunk, chunks, count);
+    hipLaunchKernelGGL(k_flag_write, dim3(chunks), dim3(256), 0, s, flags, t64, chunk, list);
+    return hipGetLastError();
+}
+
+namespace {
+template <int EX>
+void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc, const gempe::PairParams &P,
+                          float *G, float *extra, float *partials, hipStream_t s) {
+    const long long nb64 = (g->n + 63) / 64;
+    const __bf16 *xb = reinterpret_cast<const __bf16 *>(gc.xb);
+    const dim3 grid(kNearTileGrid), block(256);
+#define GEMPE_NEAR(DD)                                                                                     \
+    hipLaunchKernelGGL((k_near_tiles<DD, EX>), grid, block, 0, s, xb, X, gc.nrm, gc.smax128, g->n, nb64,  \
+                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense)
+    switch (d) {
+        case 16: GEMPE_NEAR(16); break;
+        case 32: GEMPE_NEAR(32); break;
+        case 48: GEMPE_NEAR(48); break;
+        case 64: GEMPE_NEAR(64); break;
+        case 80: GEMPE_NEAR(80); break;
+        case 96: GEMPE_NEAR(96); break;
+        case 112: GEMPE_NEAR(112); break;
+        default: GEMPE_NEAR(128); break;
+    }
+#undef GEMPE_NEAR
+}
+}  // namespace
+
+hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
+                                   const PairParamsHost &h, int ex, float *G, float *extra, float *partials,
+                                   hipStream_t s) {
+    const gempe::PairParams P{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
+                              h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2};
+    if (ex == 2)
+        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s);
+    else if (ex == 1)
+        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s);
+    else
+        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s);
     return hipGetLastError();
 }

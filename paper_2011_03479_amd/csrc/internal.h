@@ -131,6 +131,8 @@ struct WsLayout {
     size_t smax128 = 0;   // float[n/128] largest norm of every 128-vertex block
     size_t flags = 0;     // uint8[items] near flags of the 64x64 tiles
     size_t list = 0;      // int32[items] flagged tiles in order
+    size_t dense = 0;     // uint8[items] per list slot: 1 = more near pairs than the sparse pass takes
+    size_t chunks = 0;    // int32[tiles / 4096 + 1] compaction scratch
     size_t total = 0;
 };
 
@@ -151,6 +153,8 @@ struct GramCtx {
     unsigned char *flags = nullptr;
     int *list = nullptr, *count = nullptr;
     float theta0 = 0.0f;  // mu + near_k sigma
+    unsigned char *dense = nullptr;
+    int *chunks = nullptr;
 };
 GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p);
 
@@ -161,7 +165,11 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   const GramCtx &gc, double *red, float *wm_z = nullptr);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
-                                    float theta0, hipStream_t s);
+                                    float theta0, int *chunk, hipStream_t s);
+// Sparse exact pass over the flagged tiles (gram.hip); ex: 0 none, 1 row loss, 2 WM z.
+hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
+                                   const PairParamsHost &pp, int ex, float *G, float *extra, float *partials,
+                                   hipStream_t s);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s);
 // Continuous batching of fused iterations (sweep.hip): one table row per job.

@@ -357,10 +357,12 @@ template <int D, int EX>
 __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict__ X, int n, int d, int nt,
                                                         const int *__restrict__ list, const int *__restrict__ count,
                                                         float *__restrict__ G, float *__restrict__ rowloss,
-                                                        float *__restrict__ partials, PairParams P, float far2) {
+                                                        float *__restrict__ partials, PairParams P, float far2,
+                                                        const unsigned char *__restrict__ dense) {
     extern __shared__ float lds[];
     const int cnt = *count;
     for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
+        if (!dense[q]) continue;  // finished by the sparse pass (k_near_tiles)
         int I, J;
         tile_of(list[q], nt, I, J);
         float l = wide_tile<D, EX, true>(X, n, d, I, J, G, rowloss, P, lds, far2);
@@ -981,6 +983,10 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
         off = align256(off + (size_t)plan.items);
         L.list = off;
         off = align256(off + sizeof(int) * (size_t)plan.items);
+        L.dense = off;
+        off = align256(off + (size_t)plan.items);
+        L.chunks = off;
+        off = align256(off + sizeof(int) * (size_t)(plan.items / 4096 + 1));
     }
     L.total = off;
     return L;
@@ -996,6 +1002,8 @@ GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params 
     c.flags = ws + L.flags;
     c.list = reinterpret_cast<int *>(ws + L.list);
     c.count = reinterpret_cast<int *>(ws + L.counters + 32);
+    c.dense = ws + L.dense;
+    c.chunks = reinterpret_cast<int *>(ws + L.chunks);
     c.theta0 = (float)(p->mu + p->near_k * p->sigma);
     return c;
 }
@@ -1064,7 +1072,7 @@ void launch_wide_list(const SweepPlan &pl, hipStream_t s, const float *X, int n,
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sweep_wide_list<D, EX>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
-                       gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0);
+                       gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0, gc.dense);
 }
 
 template <int EX>
@@ -1110,11 +1118,14 @@ namespace {
 // per-vertex extra sum EX into `extra` (row loss or the weighted-majorization z).
 template <int EX>
 void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X, float *grad, float *extra,
-                 float *partials, unsigned long long *cnt, const PairParams &P, hipStream_t s, const GramCtx &gc) {
+                 float *partials, unsigned long long *cnt, const PairParams &P, const PairParamsHost &pph,
+                 hipStream_t s, const GramCtx &gc) {
     const int n = g->n;
-    if (plan.bf16)
+    if (plan.bf16) {
+        // near pairs of sparsely flagged tiles exactly, the dense tiles by the LDS tile pass
+        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s);
         launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
-    else
+    } else
         launch_sweep<EX>(plan, s, X, n, d, grad, extra, partials, P);
     float *epart = partials + plan.items;
     if (plan.D > 16) {
@@ -1150,15 +1161,15 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
     }
     if (plan.bf16) {
         hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.smax128, gc.flags, gc.list,
-                                                gc.count, gc.theta0, s);
+                                                gc.count, gc.theta0, gc.chunks, s);
         if (e != hipSuccess) return e;
     }
     if (wm_z)
-        launch_pass<kExZ>(g, d, plan, X, grad, wm_z, partials, cnt, P, s, gc);
+        launch_pass<kExZ>(g, d, plan, X, grad, wm_z, partials, cnt, P, pph, s, gc);
     else if (row_loss)
-        launch_pass<kExRowLoss>(g, d, plan, X, grad, row_loss, partials, cnt, P, s, gc);
+        launch_pass<kExRowLoss>(g, d, plan, X, grad, row_loss, partials, cnt, P, pph, s, gc);
     else
-        launch_pass<kExNone>(g, d, plan, X, grad, nullptr, partials, cnt, P, s, gc);
+        launch_pass<kExNone>(g, d, plan, X, grad, nullptr, partials, cnt, P, pph, s, gc);
     float *epart = partials + plan.items;
     // FP64 loss: sweep partials (for the BF16 screen only the flagged tiles' slots) + edge partials
     const long long total = plan.items + plan.edge_blocks;
