@@ -226,7 +226,8 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
             const bool any = __ballot(near) != 0ull;
             if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
         }
-        __syncthreads();  // every wave is done with buffer cur
+        // buffer cur ^ 1 was last read in the previous step, which every wave finished
+        // before that step's closing barrier: commit into it without waiting
         if (Jn < nt256) commit(Jn, cur ^ 1, regs);
         __syncthreads();
     }
