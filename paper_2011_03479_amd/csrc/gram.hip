@@ -29,6 +29,7 @@
 
 namespace gempe {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -115,15 +116,22 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
     const int r0 = I * 128;
     const float sI = smax128[I];
 
+    // Column tiles come in through raw buffer loads: the descriptor's record count is the
+    // n x D matrix, so rows past n read as zero without a compare, the per-thread offset is
+    // one register and the tile/chunk step goes into the scalar offset.
+    const __amdgpu_buffer_rsrc_t xrs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Xb, (short)0, n * D * (int)sizeof(__bf16), 0x00020000);
+    const int voff = ((tid / CH) * D + (tid % CH) * 8) * (int)sizeof(__bf16);
     auto stage = [&](int Jt, bf16x8 (&regs)[PER]) {
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
-            const int c = tid + p * NT;
-            const int row = c / CH, ch = c - row * CH;
-            bf16x8 v = {};
-            if (c < TC * CH && Jt * TC + row < n)
-                v = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(Jt * TC + row) * D + ch * 8);
-            regs[p] = v;
+            if (tid + p * NT < TC * CH) {
+                const int soff = (Jt * TC + p * (NT / CH)) * D * (int)sizeof(__bf16);
+                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(xrs, voff, soff, 0);
+                regs[p] = __builtin_bit_cast(bf16x8, v);
+            } else {
+                regs[p] = bf16x8{};
+            }
         }
     };
     auto commit = [&](int Jt, int buf, const bf16x8 (&regs)[PER]) {
