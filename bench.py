@@ -50,6 +50,50 @@ def measured_traffic(kernel: str, workload: str):
     return rec
 
 
+TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/csrc/pairfn.h",
+                   "paper_2011_03479_amd/csrc/ltab.h", "paper_2011_03479_amd/csrc/erfcx_coef.h",
+                   "paper_2011_03479_amd/csrc/millsq_coef.h", "paper_2011_03479_amd/csrc/tiles.h",
+                   "paper_2011_03479_amd/csrc/internal.h"]
+
+
+def record_traffic(outdir: str, kernel: str, workload: str, copy_bytes: int):
+    """Writes profiles/k_iter_cl3400_traffic.json from four rocprofv3 --pmc runs under
+    `outdir` (pmc_fetch, pmc_write: FETCH_SIZE / WRITE_SIZE of the bench; pmc_copy_fetch,
+    pmc_copy_write: the same counters over the --copy-probe copy of `copy_bytes` bytes).
+    Each counter is the median over the kernel's dispatches; the copy fixes the factor that
+    turns it into bytes (the copy reads and writes copy_bytes)."""
+    import csv
+    import hashlib
+    import statistics
+
+    def median_kib(sub, name):
+        path = os.path.join(outdir, sub, "run_counter_collection.csv")
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if r["Kernel_Name"].removeprefix("void ").split("(")[0] == name]
+        if not vals:
+            raise SystemExit(f"no dispatch of {name} in {path}")
+        return statistics.median(vals), len(vals)
+
+    fetch, nk = median_kib("pmc_fetch", kernel)
+    write, _ = median_kib("pmc_write", kernel)
+    cfetch, _ = median_kib("pmc_copy_fetch", "__amd_rocclr_copyBuffer")
+    cwrite, _ = median_kib("pmc_copy_write", "__amd_rocclr_copyBuffer")
+    ff = copy_bytes / 1024.0 / cfetch
+    wf = copy_bytes / 1024.0 / cwrite
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rec = {"kernel": kernel, "workload": workload, "sources": TRAFFIC_SOURCES,
+           "source_sha256": h.hexdigest(), "dispatches": nk,
+           "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
+           "copy_probe_bytes": copy_bytes, "copy_fetch_size_kib": cfetch, "copy_write_size_kib": cwrite,
+           "fetch_factor": ff, "write_factor": wf,
+           "fetch_bytes_per_launch": fetch * 1024 * ff, "write_bytes_per_launch": write * 1024 * wf,
+           "traffic_bytes_per_launch": fetch * 1024 * ff + write * 1024 * wf}
+    out = os.path.join(ROOT, "profiles", "k_iter_cl3400_traffic.json")
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 def serving_bench(num_jobs: int, load: float, budget_gib: float, oracle_every: int, oracle_max_n: int):
     """The serving mix: Poisson stream of `num_jobs` embedding requests (n log-uniform in
     [500, 50000], ER or Chung-Lu with mean degree U[8, 30], d in {2, 16, 128}, 200
@@ -146,10 +190,16 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 20 times (the reference "
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--record-traffic", default=None, metavar="DIR",
+                    help="only write the k_iter traffic record from the rocprofv3 --pmc runs under DIR "
+                         "(no GPU needed)")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic, "gempe::k_iter<2>", "cl3400", 268435456)
+        return
     if args.copy_probe:
         import torch
 

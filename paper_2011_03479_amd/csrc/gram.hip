@@ -330,9 +330,10 @@ __global__ __launch_bounds__(256) void k_flag_write(const unsigned char *__restr
 // The flagged tiles, one wave each in list order: the tile's BF16 Gram block is recomputed
 // on MFMA with the screen's operands, accumulation order and threshold, so the near test
 // picks exactly the pairs the screen saw.  A tile with at most kSparseNear near pairs is
-// finished here: each near pair, in a fixed order, is evaluated exactly in FP32 by the whole
-// wave (coordinates over lanes, the squared distance of the wide edge pass, so an edge among
-// them gets bit-identical non-edge values there) and the tile's loss goes to partial slot q.
+// finished here: its near pairs are listed in a fixed order and evaluated exactly in FP32,
+// four at a time, each by a group of 16 lanes (coordinates over lanes, group16_sqdist, the
+// squared distance of the wide edge pass, so an edge among them gets bit-identical non-edge
+// values there); the tile's loss goes to partial slot q.
 // A denser tile is marked for the exact tile pass (k_sweep_wide_list), which writes slot q.
 // ------------------------------------------------------------------------------------
 constexpr int kSparseNear = 128;
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                                                     float *__restrict__ G, float *__restrict__ extra,
                                                     float *__restrict__ partials,
                                                     unsigned char *__restrict__ dense) {
+    __shared__ int near[4][kSparseNear];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lrow = lane & 31, lk = (lane >> 5) * 8;
@@ -383,7 +385,8 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
             const float th = theta0 + 0.0078125f * (sI + smax128[min(c, n - 1) / 128]);
             hb[b] = c < n ? 0.5f * nrm[c] - 0.5f * th * th : INFINITY;
         }
-        int c = 0;
+        // the decisions as bits (a, b, r) -> 32 a + 16 b + r of a per-lane mask
+        unsigned long long dbits = 0ull;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -394,10 +397,10 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                 for (int b = 0; b < 2; ++b) {
                     const int jg = C64 * 64 + b * 32 + lrow;
                     const bool nr = ig < jg && acc[a][b][r] - ha > hb[b];
-                    c += nr ? 1 : 0;
-                    acc[a][b][r] = nr ? 1.0f : 0.0f;  // keep only the decision
+                    dbits |= (unsigned long long)nr << (32 * a + 16 * b + r);
                 }
             }
+        const int c = __popcll(dbits);
         int tot = c;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
@@ -406,43 +409,58 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
             if (lane == 0) dense[q] = 1;
         } else {
             if (lane == 0) dense[q] = 0;
+            // list the near pairs as 6+6-bit local (row, column) codes, lane by lane (each
+            // lane's decisions in bit order from its exclusive prefix count on); the list is
+            // read back only by this wave
+            int pos = c;
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(pos, off, 64);
+                if (lane >= off) pos += t;
+            }
+            pos -= c;
+            const int npair = tot;
+            while (dbits) {
+                const int k = __builtin_ctzll(dbits);
+                dbits &= dbits - 1ull;
+                const int a = k >> 5, b = (k >> 4) & 1, r = k & 15;
+                const int li = a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                near[wave][pos++] = (li << 6) | (b * 32 + lrow);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // four pairs at a time, one per group of 16 lanes
+            const int grp = lane >> 4, sub = lane & 15;
+            constexpr int C = D / 16;
+            float lsum = 0.0f;
+            for (int p0 = 0; p0 < npair; p0 += 4) {
+                const bool valid = p0 + grp < npair;
+                const int code = near[wave][valid ? p0 + grp : p0];
+                const int i = R64 * 64 + (code >> 6), j = C64 * 64 + (code & 63);
+                float xr[C], df[C];
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int k = 0; k < C; ++k) xr[k] = X[(size_t)i * D + sub + 16 * k];
+                const float r2 = gempe::group16_sqdist<C>(xr, X + (size_t)j * D, sub, D, df);
+                float dl, cc, w = 0.0f;
+                gempe::pair_eval_t<EX == 2>(r2, 1.0f, P, dl, cc, w);
+                if (valid) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        unsigned long long m = __ballot(acc[a][b][r] != 0.0f);
-                        while (m) {
-                            const int L = __builtin_ctzll(m);
-                            m &= m - 1;
-                            const int i = R64 * 64 + a * 32 + (r >> 2) * 8 + (L >> 5) * 4 + (r & 3);
-                            const int j = C64 * 64 + b * 32 + (L & 31);
-                            const float *xi = X + (size_t)i * D;
-                            const float *xj = X + (size_t)j * D;
-                            const float xi0 = lane < D ? xi[lane] : 0.0f;
-                            const float xi1 = lane + 64 < D ? xi[lane + 64] : 0.0f;
-                            const float df0 = xi0 - (lane < D ? xj[lane] : 0.0f);
-                            const float df1 = xi1 - (lane + 64 < D ? xj[lane + 64] : 0.0f);
-                            const float r2 = gempe::wave_sum(__builtin_fmaf(df1, df1, df0 * df0));
-                            float dl, cc, w = 0.0f;
-                            gempe::pair_eval_t<EX == 2>(r2, 1.0f, P, dl, cc, w);
-                            if (lane < D) {
-                                atomicAdd(&G[(size_t)i * D + lane], cc * df0);
-                                atomicAdd(&G[(size_t)j * D + lane], -(cc * df0));
-                            }
-                            if (lane + 64 < D) {
-                                atomicAdd(&G[(size_t)i * D + lane + 64], cc * df1);
-                                atomicAdd(&G[(size_t)j * D + lane + 64], -(cc * df1));
-                            }
-                            loss += dl;
-                            if (EX && lane == 0) {
-                                const float ex = (EX == 2) ? w : dl;
-                                atomicAdd(&extra[i], ex);
-                                atomicAdd(&extra[j], ex);
-                            }
+                    for (int k = 0; k < C; ++k) {
+                        atomicAdd(&G[(size_t)i * D + sub + 16 * k], cc * df[k]);
+                        atomicAdd(&G[(size_t)j * D + sub + 16 * k], -(cc * df[k]));
+                    }
+                    if (sub == 0) {
+                        lsum += dl;
+                        if (EX) {
+                            const float ex = (EX == 2) ? w : dl;
+                            atomicAdd(&extra[i], ex);
+                            atomicAdd(&extra[j], ex);
                         }
                     }
+                }
+            }
+            // the four groups' sums in a fixed order
+            loss = ((lsum + __shfl(lsum, 16, 64)) + __shfl(lsum, 32, 64)) + __shfl(lsum, 48, 64);
+            __builtin_amdgcn_wave_barrier();
         }
         if (lane == 0) partials[q] = loss;
     }

@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
         dw = wp - wn;
         if (i < j) {
             dloss = ddl;
-            hit = gempe_hash_contains(table, cap, gempe_edge_key(i, j)) ? 1u : 0u;
+            hit = hits && gempe_hash_contains(table, cap, gempe_edge_key(i, j)) ? 1u : 0u;
         }
     }
     // row sums of the gradient change (and of the row loss), one atomic per row run
@@ -476,12 +476,16 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     }
 }
 
-// Exact edge correction for wide embeddings (d > 16): one wave per CSR row, lanes over
-// coordinates (two per lane), so coordinate loads are coalesced and the row's gradient
-// change stays in registers until one atomic per coordinate.  The squared distance is a
-// wave-wide sum, so it agrees with the sweep's sequential sum to rounding (not bitwise);
-// the residual is a relative 1e-7 of dl- for that edge.
-template <int EX>
+// Exact edge correction for wide embeddings (d > 16): one wave per CSR row i, split into
+// four groups of 16 lanes that take four of the row's entries at a time (lane s of a group
+// holds coordinates s, s+16, ... of x_i and of its gradient change), so four x_j rows are in
+// flight per wave and the pair function runs once per entry per group.  The row's column
+// indices are loaded once per 64 entries, one per lane.  The squared distance is
+// group16_sqdist, the one the BF16 path's exact near-pair pass uses.  At the end the four
+// groups' gradient changes are summed (fixed order) and added with one atomic per
+// coordinate.  `hits` (membership of each pair i<j in the edge hash, a consistency check) is
+// counted only when the caller asks for it.
+template <int D, int EX>
 __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X, int n, int d,
                                                     const int64_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
@@ -489,40 +493,69 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
                                                     unsigned long long cap, float *__restrict__ G,
                                                     float *__restrict__ rowloss, float *__restrict__ partials,
                                                     unsigned long long *hits, PairParams P) {
+    constexpr int C = D / 16;
     __shared__ float wsum[4];
     __shared__ unsigned whit[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = lane >> 4, sub = lane & 15;
     const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
-    float dloss = 0.0f;
+    float dloss = 0.0f, lrow = 0.0f;
     unsigned hitc = 0;
     if (i < n) {
         const float *xi = X + (size_t)i * d;
-        const float xi0 = lane < d ? xi[lane] : 0.0f;
-        const float xi1 = lane + 64 < d ? xi[lane + 64] : 0.0f;
-        float g0 = 0.0f, g1 = 0.0f, lrow = 0.0f;
-        const long long e1 = row_ptr[i + 1];
-        for (long long e = row_ptr[i]; e < e1; ++e) {
-            const int j = col[e];
-            const float *xj = X + (size_t)j * d;
-            const float df0 = xi0 - (lane < d ? xj[lane] : 0.0f);
-            const float df1 = xi1 - (lane + 64 < d ? xj[lane + 64] : 0.0f);
-            const float r2 = wave_sum(__builtin_fmaf(df1, df1, df0 * df0));
-            float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
-            pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
-            pair_eval_t<EX == kExZ>(r2, 1.0f, P, dln, ccn, wn);
-            const float dcc = ccp - ccn;
-            g0 += dcc * df0;
-            g1 += dcc * df1;
-            const float ddl = dlp - dln;
-            if (EX) lrow += (EX == kExZ) ? wp - wn : ddl;
-            if (i < j) {
-                dloss += ddl;
-                if (lane == 0 && gempe_hash_contains(table, cap, gempe_edge_key(i, j))) ++hitc;
+        float xr[C], g[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int c = sub + 16 * k;
+            xr[k] = c < d ? xi[c] : 0.0f;
+            g[k] = 0.0f;
+        }
+        const long long e0 = row_ptr[i], e1 = row_ptr[i + 1];
+        for (long long base = e0; base < e1; base += 64) {
+            const int cnt = (int)min(64LL, e1 - base);
+            const int jl = lane < cnt ? col[base + lane] : i;
+            for (int c0 = 0; c0 < cnt; c0 += 4) {
+                const int k = c0 + grp;
+                const bool valid = k < cnt;
+                const int j = __shfl(jl, k & 63, 64);
+                float df[C];
+                const float r2 = group16_sqdist<C>(xr, X + (size_t)(valid ? j : i) * d, sub, d, df);
+                float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
+                pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
+                pair_eval_t<EX == kExZ>(r2, 1.0f, P, dln, ccn, wn);
+                const float dcc = valid ? ccp - ccn : 0.0f;
+#pragma unroll
+                for (int q = 0; q < C; ++q) g[q] = __builtin_fmaf(dcc, df[q], g[q]);
+                if (valid && sub == 0) {
+                    const float ddl = dlp - dln;
+                    if (EX) lrow += (EX == kExZ) ? wp - wn : ddl;
+                    if (i < j) {
+                        dloss += ddl;
+                        if (hits && gempe_hash_contains(table, cap, gempe_edge_key(i, j))) ++hitc;
+                    }
+                }
             }
         }
-        if (lane < d) atomicAdd(&G[(size_t)i * d + lane], g0);
-        if (lane + 64 < d) atomicAdd(&G[(size_t)i * d + lane + 64], g1);
-        if (EX && lane == 0) atomicAdd(&rowloss[i], lrow);
+        // groups 0 + 1 + 2 + 3 in that order, then one atomic per coordinate
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const float a01 = g[q] + __shfl_xor(g[q], 16, 64);
+            g[q] = a01 + __shfl_xor(a01, 32, 64);
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int c = sub + 16 * q;
+            if ((q & 3) == grp && c < d) atomicAdd(&G[(size_t)i * d + c], g[q]);
+        }
+    }
+    dloss = wave_sum(dloss);
+    if (EX) {
+        lrow = wave_sum(lrow);
+        if (i < n && lane == 0) atomicAdd(&rowloss[i], lrow);
+    }
+    if (hits) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) hitc += __shfl_xor(hitc, off, 64);
     }
     if (lane == 0) {
         wsum[wave] = dloss;
@@ -1118,7 +1151,7 @@ namespace {
 // per-vertex extra sum EX into `extra` (row loss or the weighted-majorization z).
 template <int EX>
 void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X, float *grad, float *extra,
-                 float *partials, unsigned long long *cnt, const PairParams &P, const PairParamsHost &pph,
+                 float *partials, unsigned long long *hits, const PairParams &P, const PairParamsHost &pph,
                  hipStream_t s, const GramCtx &gc) {
     const int n = g->n;
     if (plan.bf16) {
@@ -1130,12 +1163,20 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     float *epart = partials + plan.items;
     if (plan.D > 16) {
         // wide: one wave per CSR row (also writes the partial of rows without edges)
-        hipLaunchKernelGGL((k_edges_rows<EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr,
-                           g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, cnt, P);
+#define GEMPE_EDGES_ROWS(DD)                                                                              \
+    hipLaunchKernelGGL((k_edges_rows<DD, EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr, \
+                       g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, hits, P)
+        if (plan.D == 32)
+            GEMPE_EDGES_ROWS(32);
+        else if (plan.D == 64)
+            GEMPE_EDGES_ROWS(64);
+        else
+            GEMPE_EDGES_ROWS(128);
+#undef GEMPE_EDGES_ROWS
     } else if (g->nnz > 0) {
         hipLaunchKernelGGL((k_edges<EX>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
                            g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad, extra,
-                           epart, cnt, P);
+                           epart, hits, P);
     } else {
         hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, epart, (long long)plan.edge_blocks, nullptr, 0LL,
                            nullptr, 0);
@@ -1165,11 +1206,11 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
         if (e != hipSuccess) return e;
     }
     if (wm_z)
-        launch_pass<kExZ>(g, d, plan, X, grad, wm_z, partials, cnt, P, pph, s, gc);
+        launch_pass<kExZ>(g, d, plan, X, grad, wm_z, partials, hits_out ? cnt : nullptr, P, pph, s, gc);
     else if (row_loss)
-        launch_pass<kExRowLoss>(g, d, plan, X, grad, row_loss, partials, cnt, P, pph, s, gc);
+        launch_pass<kExRowLoss>(g, d, plan, X, grad, row_loss, partials, hits_out ? cnt : nullptr, P, pph, s, gc);
     else
-        launch_pass<kExNone>(g, d, plan, X, grad, nullptr, partials, cnt, P, pph, s, gc);
+        launch_pass<kExNone>(g, d, plan, X, grad, nullptr, partials, hits_out ? cnt : nullptr, P, pph, s, gc);
     float *epart = partials + plan.items;
     // FP64 loss: sweep partials (for the BF16 screen only the flagged tiles' slots) + edge partials
     const long long total = plan.items + plan.edge_blocks;

@@ -50,6 +50,36 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Sum over the 16 lanes of each DPP row, returned in all 16: rotations by 8 and 4 lanes, then
+// exchanges within quads.  Each step adds two values that the partner lane adds in the
+// other order, so every lane of the row ends with the same bits.  Call with the whole wave
+// active.
+__device__ __forceinline__ float row16_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, true));  // row_ror:8
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, true));  // row_ror:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad 2,3,0,1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad 1,0,3,2
+    return v;
+}
+
+// Squared distance of two rows by a group of 16 lanes (one DPP row): lane s of the group
+// holds coordinates s, s+16, ..., s+16(C-1) of x_i in xi (zero past d), loads the same
+// coordinates of x_j, sums its C squared differences in order with fused multiply-adds, and
+// row16_sum combines the 16 partial sums.  The wide edge pass and the exact near-pair pass
+// of the BF16 path both use it, so a pair they share gets the same bits in both.
+template <int C>
+__device__ __forceinline__ float group16_sqdist(const float (&xi)[C], const float *__restrict__ xj, int sub, int d,
+                                                float (&df)[C]) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        const int c = sub + 16 * k;
+        df[k] = xi[k] - (c < d ? xj[c] : 0.0f);
+        s = __builtin_fmaf(df[k], df[k], s);
+    }
+    return row16_sum(s);
+}
+
 // Squared distance, coordinates in order with fused multiply-adds (padding coordinates are
 // zero on both sides and add exactly 0).
 template <int D>
