@@ -57,7 +57,7 @@ typedef enum gempe_status {
 /* Arithmetic of the all-pairs sweep. */
 typedef enum gempe_precision {
     GEMPE_FP32 = 0,      /* every pair in FP32 (1 <= d <= 128)                              */
-    GEMPE_BF16_GRAM = 1  /* d >= 16, d % 16 == 0: distances screened by a BF16 MFMA Gram
+    GEMPE_BF16_GRAM = 1  /* d >= 16, d % 16 == 0, n <= 4,194,240: distances screened by a BF16 MFMA Gram
                             tile with FP32 accumulation; edges and pairs whose screened
                             distance is below mu + near_k*sigma + margin are recomputed
                             exactly in FP32, the remaining far non-edges contribute 0 */

@@ -59,6 +59,10 @@ gempe_status gempe_check_problem(int32_t n, int32_t d, const gempe_params *p, co
             return gempe_fail(GEMPE_ERR_ARG, w + ": BF16_GRAM needs d >= 16 and d % 16 == 0");
         if (!(std::isfinite(p->near_k) && p->near_k > 0.0))
             return gempe_fail(GEMPE_ERR_ARG, w + ": near_k must be finite and > 0");
+        // the 64 x 64 tiles on or above the diagonal are indexed with 32-bit integers
+        const long long nb64 = ((long long)n + 63) / 64;
+        if (nb64 * (nb64 + 1) / 2 > 2147483647LL)
+            return gempe_fail(GEMPE_ERR_ARG, w + ": BF16_GRAM supports n <= 4194240");
     }
     if (p->precision != GEMPE_FP32 && p->precision != GEMPE_BF16_GRAM)
         return gempe_fail(GEMPE_ERR_ARG, w + ": unknown precision");

@@ -83,42 +83,46 @@ __global__ __launch_bounds__(128) void k_blockmax(const float *__restrict__ snor
     if (threadIdx.x == 0) smax128[blockIdx.x] = fmaxf(w[0], w[1]);
 }
 
-// Screen of the 128-row strip I against 256-column tiles J = J0 + q, J0 + q + Q, ...
-// (item I*Q + q, J0 = I/2, the first tile reaching the diagonal).  The strip's operand
-// fragments and row terms are loaded once into registers; the column tiles stream through
-// two LDS buffers, the next tile's global loads issued before the current tile's MFMAs.
-// Eight waves, one 64 x 64 sub-tile each (rows 64 wr.., columns 64 wc.. of the tile): the
-// register budget then allows two waves per SIMD, so one wave's MFMAs cover the other's
-// LDS waits.  Writes flags[t64] (1: some pair of the 64 x 64 sub-tile may be near) for every
-// sub-tile on or above the diagonal, so the flags need no clearing between calls.
+// Screen of a strip of 64 RW rows against column tiles of 64 CW columns (CW = 8 / RW):
+// item I*Q + q takes the tiles J = J0 + q, J0 + q + Q, ... (J0: the first tile reaching the
+// strip's diagonal).  Wave w owns the 64 x 64 sub-tile (w / CW, w % CW) of every step: it
+// keeps the BF16 fragments of its 64 rows in registers for the whole item, and the column
+// tiles stream through two LDS buffers, the next tile's global loads issued before the
+// current tile's MFMAs.  A strip of 512 rows (RW = 8) reads each column tile once per 512
+// rows, a quarter of the global traffic of 128-row strips (RW = 2), which is what keeps the
+// MFMAs fed at large n; RW = 2 gives more workgroups when n is small.  Eight waves of up to
+// 256 registers: two per SIMD, so one wave's MFMAs cover the other's waits.  Writes
+// flags[t64] (1: some pair of the 64 x 64 sub-tile may be near) for every sub-tile on or
+// above the diagonal, so the flags need no clearing between calls.
 constexpr int kScreenThreads = 512;
 
-template <int D>
+template <int D, int RW>
 __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__restrict__ Xb,
                                                      const float *__restrict__ nrm,
-                                                     const float *__restrict__ smax128, int n, int nt128,
-                                                     int nt256, int Q, long long nb64, float theta0,
+                                                     const float *__restrict__ smax128, int n, int ntile,
+                                                     int Q, long long nb64, float theta0,
                                                      unsigned char *__restrict__ flags) {
+    constexpr int CW = 8 / RW;
     constexpr int S = D + 8;   // padded LDS row stride (bf16): rows fall on different banks
     constexpr int CH = D / 8;  // 16-byte chunks per row
-    constexpr int TC = 256;    // columns per tile
+    constexpr int TC = 64 * CW;  // columns per tile
     constexpr int NT = kScreenThreads;
     constexpr int PER = (TC * CH + NT - 1) / NT;  // chunks each thread stages per tile
     __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TC * S];
-    __shared__ float hA[128], hB[2][TC];
+    __shared__ float hN[2][TC], hS[2][TC];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: branches stay scalar
     const int I = blockIdx.x / Q, q = blockIdx.x % Q;
-    int J = I / 2 + q;
-    if (J >= nt256) return;  // uniform over the workgroup
-    const int r0 = I * 128;
-    const float sI = smax128[I];
+    int J = (I * RW) / CW + q;
+    if (J >= ntile) return;  // uniform over the workgroup
+    const int wr = wave / CW, wc = wave % CW;
+    const long long R64 = (long long)I * RW + wr;  // this wave's row block (>= nb64: no rows)
 
-    // Column tiles come in through raw buffer loads: the descriptor's record count is the
-    // n x D matrix, so rows past n read as zero without a compare, the per-thread offset is
-    // one register and the tile/chunk step goes into the scalar offset.
+    // Operands come in through raw buffer loads: the descriptor's record count is the n x D
+    // matrix, so rows past n read as zero without a compare, the per-thread offset is one
+    // register and the tile/chunk step goes into the scalar offset.
     const __amdgpu_buffer_rsrc_t xrs =
         __builtin_amdgcn_make_buffer_rsrc((void *)Xb, (short)0, n * D * (int)sizeof(__bf16), 0x00020000);
     const int voff = ((tid / CH) * D + (tid % CH) * 8) * (int)sizeof(__bf16);
@@ -143,50 +147,45 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
         }
         if (tid < TC) {
             const int c = Jt * TC + tid;
-            // threshold of the 128 x 128 block pair: 2^-7 (|x_i| + |x_j|) margin
-            const float th = theta0 + 0.0078125f * (sI + smax128[min(c, n - 1) / 128]);
-            hB[buf][tid] = c < n ? 0.5f * nrm[c] - 0.5f * th * th : INFINITY;
+            hN[buf][tid] = c < n ? nrm[c] : 0.0f;
+            hS[buf][tid] = smax128[min(c, n - 1) / 128];
         }
     };
 
-    // the strip's rows pass through buffer 1 into registers
-    for (int c = tid; c < 128 * CH; c += NT) {
-        const int row = c / CH, ch = c - row * CH;
-        bf16x8 v = {};
-        if (r0 + row < n) v = *reinterpret_cast<const bf16x8 *>(Xb + (size_t)(r0 + row) * D + ch * 8);
-        *reinterpret_cast<bf16x8 *>(&Bs[1][row * S + ch * 8]) = v;
-    }
-    if (tid < 128) hA[tid] = (r0 + tid < n) ? 0.5f * nrm[r0 + tid] : INFINITY;
-    __syncthreads();
-    const int wr = wave >> 2, wc = wave & 3;
+    // this wave's rows: fragments, row terms and the 128-row block's largest |x|
     const int lrow = lane & 31, lk = (lane >> 5) * 8;
     bf16x8 afr[D / 16][2];
 #pragma unroll
-    for (int kk = 0; kk < D / 16; ++kk) {
-        afr[kk][0] = *reinterpret_cast<const bf16x8 *>(&Bs[1][(wr * 64 + lrow) * S + kk * 16 + lk]);
-        afr[kk][1] = *reinterpret_cast<const bf16x8 *>(&Bs[1][(wr * 64 + 32 + lrow) * S + kk * 16 + lk]);
-    }
+    for (int kk = 0; kk < D / 16; ++kk)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int row = (int)R64 * 64 + a * 32 + lrow;
+            const int off = (row * D + kk * 16 + lk) * (int)sizeof(__bf16);
+            afr[kk][a] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xrs, off, 0, 0));
+        }
     float ha[2][16];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) ha[a][r] = hA[wr * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)];
+        for (int r = 0; r < 16; ++r) {
+            const long long ig = R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            ha[a][r] = ig < n ? 0.5f * nrm[ig] : INFINITY;
+        }
+    const float sI = R64 < nb64 ? smax128[R64 / 2] : 0.0f;
     {
         bf16x8 regs[PER];
         stage(J, regs);
-        __syncthreads();  // buffer 1 is free again
         commit(J, 0, regs);
     }
     __syncthreads();
 
-    const long long R64 = 2LL * I + wr;
-    for (int it = 0; J < nt256; ++it, J += Q) {
+    for (int it = 0; J < ntile; ++it, J += Q) {
         const int cur = it & 1;
         const int Jn = J + Q;
         bf16x8 regs[PER];
-        if (Jn < nt256) stage(Jn, regs);
+        if (Jn < ntile) stage(Jn, regs);
 
-        const long long C64 = 4LL * J + wc;  // this wave's sub-tile column
+        const long long C64 = (long long)J * CW + wc;  // this wave's sub-tile column
         if (R64 <= C64 && C64 < nb64) {
             floatx16 acc[2][2];
 #pragma unroll
@@ -207,20 +206,23 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
             }
             // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block;
             // near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>  delta~^2 < theta^2, taken on the
-            // largest G~ - n~_i/2 of the lane's column (one compare per column)
+            // largest G~ - n~_i/2 of the lane's column (one compare per column); theta carries
+            // the 2^-7 (|x_i| + |x_j|) margin of the two 128-vertex blocks
             const bool diag = (R64 == C64);
             bool near = false;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int jl = wc * 64 + b * 32 + (lane & 31);
+                const int jg = J * TC + jl;
+                const float th = theta0 + 0.0078125f * (sI + hS[cur][jl]);
+                const float hb = jg < n ? 0.5f * hN[cur][jl] - 0.5f * th * th : INFINITY;
                 float m = -INFINITY;
                 if (diag) {  // only pairs i < j of a diagonal sub-tile
-                    const int jg = J * TC + jl;
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            const int ig = r0 + wr * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                            const int ig = (int)R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
                             m = fmaxf(m, ig < jg ? acc[a][b][r] - ha[a][r] : -INFINITY);
                         }
                 } else {
@@ -229,14 +231,14 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
 #pragma unroll
                         for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r] - ha[a][r]);
                 }
-                near = near || (m > hB[cur][jl]);
+                near = near || (m > hb);
             }
             const bool any = __ballot(near) != 0ull;
             if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
         }
         // buffer cur ^ 1 was last read in the previous step, which every wave finished
         // before that step's closing barrier: commit into it without waiting
-        if (Jn < nt256) commit(Jn, cur ^ 1, regs);
+        if (Jn < ntile) commit(Jn, cur ^ 1, regs);
         __syncthreads();
     }
 }
@@ -479,13 +481,21 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
     const int nt128 = (n + 127) / 128;
     hipLaunchKernelGGL(k_blockmax, dim3((unsigned)nt128), dim3(128), 0, s, snorm, n, smax128);
     const long long nb64 = (n + 63) / 64;
-    const int nt256 = (n + 255) / 256;
-    // Q column tiles interleaved per strip: enough workgroups to fill the chip, strips
-    // long enough to amortise the resident rows
-    const int Q = std::max(1, std::min(8, nt256 / 2));
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(Xb);
-    dim3 grid((unsigned)((long long)nt128 * Q)), block(kScreenThreads);
-#define GEMPE_SCREEN(DD) hipLaunchKernelGGL(k_gram_screen<DD>, grid, block, 0, s, xb, nrm, smax128, n, nt128, nt256, Q, nb64, theta0, flags)
+    // 512-row strips once there are enough of them to fill the chip with Q = 8 column
+    // phases each, else 128-row strips; Q column tiles interleaved per strip
+    const bool tall = (n + 511) / 512 >= 64;
+    const int RW = tall ? 8 : 2, TC = 64 * (8 / RW);
+    const int nstrip = (n + 64 * RW - 1) / (64 * RW), ntile = (n + TC - 1) / TC;
+    const int Q = tall ? 8 : std::max(1, std::min(8, ntile / 2));
+    dim3 grid((unsigned)((long long)nstrip * Q)), block(kScreenThreads);
+#define GEMPE_SCREEN(DD)                                                                                          \
+    if (tall)                                                                                                     \
+        hipLaunchKernelGGL((k_gram_screen<DD, 8>), grid, block, 0, s, xb, nrm, smax128, n, ntile, Q, nb64, theta0, \
+                           flags);                                                                                \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_gram_screen<DD, 2>), grid, block, 0, s, xb, nrm, smax128, n, ntile, Q, nb64, theta0, \
+                           flags)
     switch (d) {
         case 16: GEMPE_SCREEN(16); break;
         case 32: GEMPE_SCREEN(32); break;

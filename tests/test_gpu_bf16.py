@@ -102,3 +102,21 @@ def test_sbm100k_sampled_rows():
     G = gempe.Graph(g.n, g.row_ptr, g.col_idx)
     check_rows(g, G, w.X0, rows, params=gempe.params_default(**BF16), what="sbm100k",
                loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL, grad_atol=(g.n - 1) * BF16_FLUSH_GRAD)
+
+
+@pytest.mark.parametrize("n,d", [(40000, 32), (33000, 128)])
+def test_bf16_tall_strips_clusters(n, d):
+    """n >= 32,768 selects the 512-row screen strips (the last strip partly past n); tight
+    clusters make most flagged tiles sparse.  Sampled rows against the oracle."""
+    X, lab = clusters(n, d, 40, spread=0.1, sep=3.0, seed=n + d)
+    rng = np.random.default_rng(n)
+    u = rng.integers(0, n, 3 * n)
+    members = [np.nonzero(lab == k)[0] for k in range(40)]
+    same = np.array([rng.choice(members[lab[a]]) for a in u[:2 * n]])
+    vv = np.concatenate([same, rng.integers(0, n, n)])
+    g = synth.csr_from_edges(n, u, vv)
+    rows = np.unique(np.concatenate([rng.choice(n, 100, replace=False), [0, n - 1]]))
+    note(f"bf16 tall strips n={n} d={d} m={g.m}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    check_rows(g, G, X, rows, params=gempe.params_default(**BF16), what=f"bf16 tall n{n} d{d}",
+               loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL, grad_atol=(n - 1) * BF16_FLUSH_GRAD)
