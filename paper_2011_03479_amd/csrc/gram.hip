@@ -163,37 +163,22 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
             const int off = (row * D + kk * 16 + lk) * (int)sizeof(__bf16);
             afr[kk][a] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xrs, off, 0, 0));
         }
-    float ha[2][16];
+    // -n~_i / 2 in accumulator layout: the MFMA chains start from it, so they end at
+    // G~_ij - n~_i / 2 (rows past n: -inf, never near)
+    floatx16 nha[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const long long ig = R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-            ha[a][r] = ig < n ? 0.5f * nrm[ig] : INFINITY;
+            nha[a][r] = ig < n ? -(0.5f * nrm[ig]) : -INFINITY;
         }
     const float sI = R64 < nb64 ? smax128[R64 / 2] : 0.0f;
-    {
-        bf16x8 regs[PER];
-        stage(J, regs);
-        commit(J, 0, regs);
-    }
-    __syncthreads();
-
-    for (int it = 0; J < ntile; ++it, J += Q) {
-        const int cur = it & 1;
-        const int Jn = J + Q;
-        bf16x8 regs[PER];
-        if (Jn < ntile) stage(Jn, regs);
-
-        const long long C64 = (long long)J * CW + wc;  // this wave's sub-tile column
+    // the 64 x 64 sub-tile of column tile Jt held in LDS buffer cur
+    auto screen_tile = [&](int Jt, int cur) {
+        const long long C64 = (long long)Jt * CW + wc;  // this wave's sub-tile column
         if (R64 <= C64 && C64 < nb64) {
-            floatx16 acc[2][2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+            floatx16 acc[2][2] = {{nha[0], nha[0]}, {nha[1], nha[1]}};
             const __bf16 *Bc = Bs[cur];
 #pragma unroll
             for (int kk = 0; kk < D / 16; ++kk) {
@@ -204,16 +189,16 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
                 acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b0, acc[1][0], 0, 0, 0);
                 acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b1, acc[1][1], 0, 0, 0);
             }
-            // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block;
-            // near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>  delta~^2 < theta^2, taken on the
-            // largest G~ - n~_i/2 of the lane's column (one compare per column); theta carries
-            // the 2^-7 (|x_i| + |x_j|) margin of the two 128-vertex blocks
+            // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block,
+            // holding G~ - n~_i/2; near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>
+            // delta~^2 < theta^2, taken on the lane's largest value (one compare per column);
+            // theta carries the 2^-7 (|x_i| + |x_j|) margin of the two 128-vertex blocks
             const bool diag = (R64 == C64);
             bool near = false;
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const int jl = wc * 64 + b * 32 + (lane & 31);
-                const int jg = J * TC + jl;
+                const int jg = Jt * TC + jl;
                 const float th = theta0 + 0.0078125f * (sI + hS[cur][jl]);
                 const float hb = jg < n ? 0.5f * hN[cur][jl] - 0.5f * th * th : INFINITY;
                 float m = -INFINITY;
@@ -223,23 +208,63 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
                             const int ig = (int)R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                            m = fmaxf(m, ig < jg ? acc[a][b][r] - ha[a][r] : -INFINITY);
+                            m = fmaxf(m, ig < jg ? acc[a][b][r] : -INFINITY);
                         }
                 } else {
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r] - ha[a][r]);
+                        for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r]);
                 }
                 near = near || (m > hb);
             }
             const bool any = __ballot(near) != 0ull;
             if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
         }
-        // buffer cur ^ 1 was last read in the previous step, which every wave finished
-        // before that step's closing barrier: commit into it without waiting
-        if (Jn < ntile) commit(Jn, cur ^ 1, regs);
+    };
+
+    if constexpr (PER <= 2) {
+        // global loads two steps ahead (two staging register sets): a load has a whole step
+        // of MFMAs more to arrive before its commit
+        bf16x8 ra[PER], rb[PER];
+        stage(J, ra);
+        commit(J, 0, ra);
+        if (J + Q < ntile) stage(J + Q, ra);
         __syncthreads();
+        for (;;) {
+            // tile J in buffer 0, tile J + Q arriving in ra
+            if (J + 2 * Q < ntile) stage(J + 2 * Q, rb);
+            screen_tile(J, 0);
+            if (J + Q < ntile) commit(J + Q, 1, ra);
+            __syncthreads();
+            J += Q;
+            if (J >= ntile) break;
+            // tile J in buffer 1, tile J + Q arriving in rb
+            if (J + 2 * Q < ntile) stage(J + 2 * Q, ra);
+            screen_tile(J, 1);
+            if (J + Q < ntile) commit(J + Q, 0, rb);
+            __syncthreads();
+            J += Q;
+            if (J >= ntile) break;
+        }
+    } else {
+        {
+            bf16x8 regs[PER];
+            stage(J, regs);
+            commit(J, 0, regs);
+        }
+        __syncthreads();
+        for (int it = 0; J < ntile; ++it, J += Q) {
+            const int cur = it & 1;
+            const int Jn = J + Q;
+            bf16x8 regs[PER];
+            if (Jn < ntile) stage(Jn, regs);
+            screen_tile(J, cur);
+            // buffer cur ^ 1 was last read in the previous step, which every wave finished
+            // before that step's closing barrier: commit into it without waiting
+            if (Jn < ntile) commit(Jn, cur ^ 1, regs);
+            __syncthreads();
+        }
     }
 }
 
@@ -330,7 +355,7 @@ __global__ __launch_bounds__(256) void k_flag_write(const unsigned char *__restr
 
 // ------------------------------------------------------------------------------------
 // The flagged tiles, one wave each in list order: the tile's BF16 Gram block is recomputed
-// on MFMA with the screen's operands, accumulation order and threshold, so the near test
+// on MFMA with the screen's operands, starting values, accumulation order and threshold, so the near test
 // picks exactly the pairs the screen saw.  A tile with at most kSparseNear near pairs is
 // finished here: its near pairs are listed in a fixed order and evaluated exactly in FP32,
 // four at a time, each by a group of 16 lanes (coordinates over lanes, group16_sqdist, the
@@ -362,9 +387,10 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+            for (int r = 0; r < 16; ++r) {
+                const int ig = R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                acc[a][0][r] = acc[a][1][r] = ig < n ? -(0.5f * nrm[ig]) : -INFINITY;
+            }
 #pragma unroll
         for (int kk = 0; kk < D / 16; ++kk) {
             bf16x8 a0 = {}, a1 = {}, b0 = {}, b1 = {};
@@ -394,11 +420,10 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int ig = R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                const float ha = ig < n ? 0.5f * nrm[ig] : INFINITY;
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     const int jg = C64 * 64 + b * 32 + lrow;
-                    const bool nr = ig < jg && acc[a][b][r] - ha > hb[b];
+                    const bool nr = ig < jg && acc[a][b][r] > hb[b];
                     dbits |= (unsigned long long)nr << (32 * a + 16 * b + r);
                 }
             }
