@@ -114,10 +114,12 @@ __device__ __forceinline__ void pair_nonedge(float r2, const PairParams &P, floa
 // Non-edge pair from the piecewise-cubic table of L = log2 dl(tau) (ltab.h), staged in LDS
 // as float4 pairs {n0, r0, a1, a2}, {a3, k d1, k d2, k d3} per segment of width 1/16 in
 // tau, with k = ln2 / sigma folded in by the staging:
-//   16 tau = tk_scale delta + tk_off,  segment = floor(16 tau) + zero,  f = fract(16 tau)
+//   16 tau + zero = tk_scale delta + tko,  segment = floor of that,  f = its fraction
 //   dl = 2^n0 2^(r0 + f(a1 + f(a2 + f a3))),  d dl/d delta = dl k (d1 + f(d2 + f d3))
-// Two transcendentals (rsq, exp2) instead of five; 16 tau is exact in FP32, so f carries
-// every bit of tau.  Returns false when tau is outside the table (dl, cc unspecified).
+// (tko = tk_off + zero from table_offset, zero = the segment of tau = 0).  Two
+// transcendentals (rsq, exp2) instead of five.  r2 must be positive: the sweeps' squared
+// distances start from FLT_MIN (sqdist_eps), which keeps rsq finite for coincident points.
+// Returns false when tau is outside the table (dl, cc unspecified).
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int floor_to_int(float x) {
     int k;
@@ -125,17 +127,25 @@ __device__ __forceinline__ int floor_to_int(float x) {
     return k;
 }
 
+// tk_off + zero, in a vector register: the index fma then reads a single scalar operand,
+// which GFX9 encodings allow, instead of copying a second one into a VGPR for every pair.
+__device__ __forceinline__ float table_offset(const PairParams &P, int zero) {
+    float t = P.tk_off + (float)zero;
+    asm("" : "+v"(t));
+    return t;
+}
+
 template <bool W>
 __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, const float4 *__restrict__ tab,
-                                                 int zero, unsigned segs, float &dl, float &cc, float &w) {
-    float r2c = r2 + kFltMin;
-    float rinv = hw_rsq(r2c);
-    float delta = r2c * rinv;
-    float tk = __builtin_fmaf(delta, P.tk_scale, P.tk_off);
+                                                 float tko, unsigned segs, float &dl, float &cc, float &w) {
+    float rinv = hw_rsq(r2);
+    float delta = r2 * rinv;
+    float tk = __builtin_fmaf(delta, P.tk_scale, tko);
     float f = __builtin_amdgcn_fractf(tk);
-    const unsigned idx = (unsigned)(floor_to_int(tk) + zero);
-    const bool ok = idx < segs;
-    const unsigned off = ok ? (idx << 5) : 0u;  // byte offset of the segment's two float4
+    const int k = floor_to_int(tk);
+    const bool ok = (unsigned)k < segs;
+    // byte offset of the segment's two float4, clamped into the table for lanes outside it
+    const unsigned off = min((unsigned)k << 5, (segs - 1u) << 5);
     const float4 *e = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + off);
     const float4 A = e[0], B = e[1];
     float r = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(B.x, f, A.w), f, A.z), f, A.y);
@@ -144,7 +154,7 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
     const float c1 = dl * D;  // d dl / d delta
     cc = c1 * rinv;
     // w = R (R + tau) / (2 sigma^2 ln 2) with R = -sigma ln2 c1:  w = c1 (ln2/2 c1 - tau/(2 sigma))
-    if (W) w = c1 * __builtin_fmaf(0.34657359028f, c1, tk * P.wk2);
+    if (W) w = c1 * __builtin_fmaf(0.34657359028f, c1, __builtin_fmaf(delta, P.tk_scale, P.tk_off) * P.wk2);
     return ok;
 }
 
@@ -153,8 +163,8 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
 // sweep and the edge pass subtract exactly what the other added.
 template <bool W>
 __device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,
-                                             int zero, unsigned segs, float &dl, float &cc, float &w) {
-    const bool ok = pair_nonedge_tab<W>(r2, P, tab, zero, segs, dl, cc, w);
+                                             float tko, unsigned segs, float &dl, float &cc, float &w) {
+    const bool ok = pair_nonedge_tab<W>(r2, P, tab, tko, segs, dl, cc, w);
     if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
         float dl2, cc2, w2;
         pair_eval_t<W>(r2, 1.0f, P, dl2, cc2, w2);

@@ -60,9 +60,9 @@ __device__ __forceinline__ void stage_ltab(float4 *dst, float slope_k) {
 }
 
 template <bool W = false>
-__device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float &dl, float &cc,
-                                        float &w) {
-    nonedge_eval<W>(r2, P, tab, kLtabZero, kLtabSegs, dl, cc, w);
+__device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float tko, float &dl,
+                                        float &cc, float &w) {
+    nonedge_eval<W>(r2, P, tab, tko, kLtabSegs, dl, cc, w);
 }
 
 // What the per-vertex "extra" output of a sweep accumulates (the array called rowloss /
@@ -97,6 +97,7 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
                                             float (&li)[R], float &loss, int lane, int dir, int col0, int n,
                                             int s0, int s1, const PairParams &P, const float4 *tab) {
     constexpr int NC = D + (EX != 0 ? 1 : 0);
+    const float tko = table_offset(P, kLtabZero);
     for (int s = s0; s < s1; ++s) {
         int j = 0;
         if (MASK) j = col0 + ((lane + dir * s) & 63);
@@ -104,9 +105,9 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float diff[D];
-            float r2 = sqdist<D>(xi[r], xc, diff);
+            float r2 = sqdist_eps<D>(xi[r], xc, diff);
             float dl, cc, w = 0.0f;
-            nonedge<EX == kExZ>(r2, P, tab, dl, cc, w);
+            nonedge<EX == kExZ>(r2, P, tab, tko, dl, cc, w);
             if (MASK) {
                 bool valid = (irow[r] < j) && (j < n);
                 dl = valid ? dl : 0.0f;
@@ -384,10 +385,10 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
         xi[k] = k < xv.d ? xv.at(i, k) : 0.0f;
         xj[k] = k < xv.d ? xv.at(j, k) : 0.0f;
     }
-    float r2 = sqdist<D>(xi, xj, diff);
+    float r2 = sqdist_eps<D>(xi, xj, diff);
     float dlp, ccp, dln, ccn, wn;
     pair_eval(r2, -1.0f, P, dlp, ccp);
-    nonedge(r2, P, tab, dln, ccn, wn);
+    nonedge(r2, P, tab, table_offset(P, kLtabZero), dln, ccn, wn);
     const float dcc = ccp - ccn;
 #pragma unroll
     for (int k = 0; k < D; ++k) dg[k] = dcc * diff[k];
@@ -435,14 +436,14 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
         j = col[e];
         const float *xi = X + (size_t)i * d;
         const float *xj = X + (size_t)j * d;
-        float r2 = 0.0f;
+        float r2 = 1.17549435e-38f;  // from FLT_MIN, as the sweeps' sqdist_eps
         for (int k = 0; k < d; ++k) {
             float df = xi[k] - xj[k];
             r2 = __builtin_fmaf(df, df, r2);
         }
         float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
         pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
-        nonedge<EX == kExZ>(r2, P, ltab, dln, ccn, wn);
+        nonedge<EX == kExZ>(r2, P, ltab, table_offset(P, kLtabZero), dln, ccn, wn);
         dcc = ccp - ccn;
         ddl = dlp - dln;
         dw = wp - wn;

@@ -80,6 +80,20 @@ __device__ __forceinline__ float group16_sqdist(const float (&xi)[C], const floa
     return row16_sum(s);
 }
 
+// The same sum started from FLT_MIN instead of 0: positive for coincident points (so the
+// table pair function's rsq stays finite) and equal to sqdist wherever sqdist > 2^-101.
+// The d <= 16 sweeps and their edge corrections use it, so both see the same bits.
+template <int D>
+__device__ __forceinline__ float sqdist_eps(const float (&a)[D], const float (&b)[D], float (&diff)[D]) {
+    float r2 = 1.17549435e-38f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        diff[k] = a[k] - b[k];
+        r2 = __builtin_fmaf(diff[k], diff[k], r2);
+    }
+    return r2;
+}
+
 // Squared distance, coordinates in order with fused multiply-adds (padding coordinates are
 // zero on both sides and add exactly 0).
 template <int D>
