@@ -109,7 +109,8 @@ struct SweepPlan {
     bool persist = false;
     long long nb64 = 0;        // 64-vertex blocks per side
     long long tiles64 = 0;     // upper-triangle 64x64 tiles
-    long long units_sweep = 0, units_edge = 0, units = 0;  // workgroups per iteration
+    long long units_sweep = 0, units_edge = 0, units = 0;  // work units per iteration
+    long long iter_blocks = 0;  // workgroups per iteration: the units + one that sums the loss
     // BF16 Gram screen (precision GEMPE_BF16_GRAM): items = 64x64 upper tiles, D = padded
     // dimension of the exact pass over the flagged tiles
     bool bf16 = false;

@@ -35,7 +35,7 @@ struct PairParams {
     float c_pos;      // 1/sqrt(2 pi) * d1s
     float tk_scale;   // table index scale 16 / sigma   (16 tau = tk_scale delta + tk_off)
     float tk_off;     // -16 mu / sigma
-    float slope_k;    // ln 2 / sigma
+    float slope_k;    // 16 ln 2 / sigma      (d dl/d delta = dl slope_k dL/df of the table)
     float r_scale;    // -sigma ln 2          (R = phi/Phi from the slope term)
     float w_scale;    // 1 / (2 sigma^2 ln 2) (w = dl''/2 = R (R + tau) w_scale)
     float wk2;        // -1 / (32 sigma)      (table form of w, see pair_nonedge_tab)
@@ -112,14 +112,14 @@ __device__ __forceinline__ void pair_nonedge(float r2, const PairParams &P, floa
 
 // ------------------------------------------------------------------------------------
 // Non-edge pair from the piecewise-cubic table of L = log2 dl(tau) (ltab.h), staged in LDS
-// as float4 pairs {n0, r0, a1, a2}, {a3, k d1, k d2, k d3} per segment of width 1/16 in
-// tau, with k = ln2 / sigma folded in by the staging:
+// as one float4 {c0, c1, c2, c3} per segment of width 1/16 in tau:
 //   16 tau + zero = tk_scale delta + tko,  segment = floor of that,  f = its fraction
-//   dl = 2^n0 2^(r0 + f(a1 + f(a2 + f a3))),  d dl/d delta = dl k (d1 + f(d2 + f d3))
+//   dl = 2^(c0 + f(c1 + f(c2 + f c3))),  d dl/d delta = dl slope_k (c1 + f(2 c2 + 3 c3 f))
 // (tko = tk_off + zero from table_offset, zero = the segment of tau = 0).  Two
-// transcendentals (rsq, exp2) instead of five.  r2 must be positive: the sweeps' squared
-// distances start from FLT_MIN (sqdist_eps), which keeps rsq finite for coincident points.
-// Returns false when tau is outside the table (dl, cc unspecified).
+// transcendentals (rsq, exp2) instead of five and one 16-byte LDS gather per pair.  r2
+// must be positive: the sweeps' squared distances start from FLT_MIN (sqdist_eps), which
+// keeps rsq finite for coincident points.  Returns false when tau is below the table
+// (dl, cc unspecified); from the table's top on (dl < 2^-150) it returns dl = cc = 0.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int floor_to_int(float x) {
     int k;
@@ -143,23 +143,28 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
     float tk = __builtin_fmaf(delta, P.tk_scale, tko);
     float f = __builtin_amdgcn_fractf(tk);
     const int k = floor_to_int(tk);
-    const bool ok = (unsigned)k < segs;
-    // byte offset of the segment's two float4, clamped into the table for lanes outside it
-    const unsigned off = min((unsigned)k << 5, (segs - 1u) << 5);
-    const float4 *e = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + off);
-    const float4 A = e[0], B = e[1];
-    float r = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(B.x, f, A.w), f, A.z), f, A.y);
-    float D = __builtin_fmaf(__builtin_fmaf(B.w, f, B.z), f, B.y);
-    dl = __builtin_amdgcn_ldexpf(hw_exp2(r), __float_as_int(A.x));
-    const float c1 = dl * D;  // d dl / d delta
-    cc = c1 * rinv;
+    const bool ok = k >= 0;
+    // byte offset of the segment's float4; indices past the last segment (and, for lanes
+    // that fall back, negative ones) read the all-zero segment `segs`
+    const unsigned off = min((unsigned)k, segs) << 4;
+    const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + off);
+    // L and dL/df share p = c3 f, q = c2 + p:  L = c0 + f (c1 + f q),  dL/df = c1 + f (2q + p)
+    const float p = c.w * f;
+    const float q = c.z + p;
+    const float L = __builtin_fmaf(__builtin_fmaf(q, f, c.y), f, c.x);
+    const float Lf = __builtin_fmaf(__builtin_fmaf(q, 2.0f, p), f, c.y);
+    dl = hw_exp2(L);
+    cc = dl * (Lf * (P.slope_k * rinv));  // (d dl / d delta) / delta, one multiply after the exp2
     // w = R (R + tau) / (2 sigma^2 ln 2) with R = -sigma ln2 c1:  w = c1 (ln2/2 c1 - tau/(2 sigma))
-    if (W) w = c1 * __builtin_fmaf(0.34657359028f, c1, __builtin_fmaf(delta, P.tk_scale, P.tk_off) * P.wk2);
+    if (W) {
+        const float c1 = (dl * Lf) * P.slope_k;  // d dl / d delta
+        w = c1 * __builtin_fmaf(0.34657359028f, c1, __builtin_fmaf(delta, P.tk_scale, P.tk_off) * P.wk2);
+    }
     return ok;
 }
 
-// The non-edge value every sweep and edge correction of d <= 16 uses: the table where tau
-// is inside it, else (per lane) the closed form.  A deterministic function of r2, so the
+// The non-edge value every sweep and edge correction of d <= 16 uses: the table for tau
+// from its bottom up, else (per lane) the closed form.  A deterministic function of r2, so the
 // sweep and the edge pass subtract exactly what the other added.
 template <bool W>
 __device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,

@@ -324,7 +324,7 @@ bool gempe_server_s::enqueue_tick() {
                                        reinterpret_cast<float *>(j->base + j->J.X), j->iters, j->eta,
                                        reinterpret_cast<double *>(j->base + j->J.hist), j->L, j->base + j->J.ws,
                                        gempe_pair_params(&j->params), blocks, j->k0);
-                blocks += std::max<long long>(1, j->plan.units);
+                blocks += j->plan.iter_blocks;
             }
             hipError_t e = hipMemcpyAsync(tables[c], stage, v.size() * eb, hipMemcpyHostToDevice, batch_stream);
             if (e != hipSuccess) {
@@ -334,7 +334,7 @@ bool gempe_server_s::enqueue_tick() {
             slot_tick[slot] = t;
             table_dirty[c] = false;
         } else {
-            for (Job *j : v) blocks += std::max<long long>(1, j->plan.units);
+            for (Job *j : v) blocks += j->plan.iter_blocks;
         }
         hipError_t e = gempe_launch_iter_batch(kDValues[c], tables[c], (int)v.size(), blocks, (int)t, batch_stream);
         if (e != hipSuccess) {

@@ -40,23 +40,15 @@
 
 namespace gempe {
 
-// The non-edge table (ltab.h) as float4 pairs, staged into LDS by every workgroup that
-// sweeps or corrects edges for d <= 16.
-constexpr int kLtabF4 = 2 * GEMPE_LTAB_SEGS;
+// The non-edge table (ltab.h), one float4 per segment, staged into LDS by every workgroup
+// that sweeps or corrects edges for d <= 16.
+constexpr int kLtabF4 = GEMPE_LTAB_SEGS + 1;  // the segments and the all-zero one past them
 constexpr int kLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
 constexpr unsigned kLtabSegs = GEMPE_LTAB_SEGS;
 
-__device__ __forceinline__ void stage_ltab(float4 *dst, float slope_k) {
+__device__ __forceinline__ void stage_ltab(float4 *dst) {
     const float4 *src = reinterpret_cast<const float4 *>(kLtab);
-    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) {
-        float4 v = src[q];
-        if (q & 1) {  // {a3, d1, d2, d3}: the derivative in d/d delta units, ln2 / sigma folded in
-            v.y *= slope_k;
-            v.z *= slope_k;
-            v.w *= slope_k;
-        }
-        dst[q] = v;
-    }
+    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) dst[q] = src[q];
 }
 
 template <bool W = false>
@@ -152,7 +144,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
-    stage_ltab(ltab, P.slope_k);
+    stage_ltab(ltab);
     __syncthreads();
     int I, J;
     tile_of(t, nt, I, J);
@@ -424,7 +416,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
     __shared__ float wsum[kEdgeBlock / 64];
     __shared__ unsigned whit[kEdgeBlock / 64];
     __shared__ float4 ltab[kLtabF4];
-    stage_ltab(ltab, P.slope_k);
+    stage_ltab(ltab);
     __syncthreads();
     long long e = (long long)blockIdx.x * kEdgeBlock + threadIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -666,7 +658,8 @@ __global__ void k_axpy(float *__restrict__ X, const float *__restrict__ G, float
 // and applies the previous step on the fly, x_k = X_{k-1} - eta G_{k-1}.  It accumulates
 // G_k into slot k%3, writes x_k into slot k&1 for iteration k+1, clears slot (k+1)%3 (the
 // slot of G_{k-2}, last read by iteration k-1), and writes one FP32 loss partial per work
-// unit into partial slot k&1; workgroup 0 sums the partials of iteration k-1 in FP64.
+// unit into partial slot k&1; one extra workgroup after the units sums the partials
+// of iteration k-1 in FP64.
 // A workgroup takes one 64 x 64 tile, its four waves a quarter of the 64-step schedule
 // each (one per SIMD), and combines their row and column partials in LDS before one
 // global flush; edge workgroups take 4 x 64 CSR entries.  The hardware dispatcher
@@ -720,8 +713,6 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const long long nd = (long long)a.n * a.d;
-    stage_ltab(L.tab, a.P.slope_k);
-    __syncthreads();
     float *Xs[2] = {a.Xc, a.Xw};
     const float *Xprev = (k == 0) ? a.Xc : Xs[(k - 1) & 1];
     const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
@@ -730,12 +721,18 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     float *Pk = a.P0 + (size_t)(k & 1) * a.units;
     const XView xv{Xprev, Gprev, a.neg_eta, a.d};
 
-    if (b == 0 && k > 0 && a.loss_hist) reduce_loss(a, k - 1, sh);
     for (long long v = gtid; v < nd; v += nthreads) {
         if (k > 0) Xs[k & 1][v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
         Gnext[v] = 0.0f;
     }
-    if (b >= a.units) return;  // uniform over the workgroup
+    if (b >= a.units) {  // uniform over the workgroup
+        // the last workgroup sums iteration k-1's loss partials, beside the tiles rather
+        // than before one of them
+        if (b == a.units && k > 0 && a.loss_hist) reduce_loss(a, k - 1, sh);
+        return;
+    }
+    stage_ltab(L.tab);
+    __syncthreads();
     float loss = 0.0f;
     if (b < a.units_edge) {
         // edge workgroups come first: their dependent gathers overlap the tiles
@@ -980,6 +977,7 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
         p.units_edge = (g->nnz + 4 * kEdgesPerUnit - 1) / (4 * kEdgesPerUnit);
         p.units_sweep = t64;
         p.units = p.units_sweep + p.units_edge;
+        p.iter_blocks = p.units + 1;
     }
     return p;
 }
@@ -1051,7 +1049,7 @@ PairParamsHost gempe_pair_params(const gempe_params *p) {
     h.c_pos = (float)(0.39894228040143267794 * d1s);  // 1/sqrt(2 pi)
     h.tk_scale = (float)(GEMPE_LTAB_INV_H / p->sigma);
     h.tk_off = (float)(-GEMPE_LTAB_INV_H * p->mu / p->sigma);
-    h.slope_k = (float)(0.69314718055994530942 / p->sigma);
+    h.slope_k = (float)(GEMPE_LTAB_INV_H * 0.69314718055994530942 / p->sigma);
     h.r_scale = (float)(-p->sigma * 0.69314718055994530942);
     h.w_scale = (float)(1.0 / (2.0 * p->sigma * p->sigma * 0.69314718055994530942));
     h.wk2 = (float)(-1.0 / (32.0 * p->sigma));
@@ -1138,7 +1136,7 @@ void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int
 
 template <int D>
 void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_t s) {
-    const unsigned grid = (unsigned)std::max<long long>(1, pl.units);
+    const unsigned grid = (unsigned)pl.iter_blocks;
     for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_iter<D>, dim3(grid), dim3(256), 0, s, a, k);
     const long long nd = (long long)a.n * a.d;
     const unsigned fgrid = (unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256));
@@ -1268,7 +1266,7 @@ void gempe_batch_entry_fill(void *dst, const gempe_graph_s *g, int d, const Swee
     BatchEntry e{};
     e.a = make_iter_args(g, d, plan, X, eta, loss_hist, L, ws, pph);
     e.u0 = u0;
-    e.blocks = std::max<long long>(1, plan.units);
+    e.blocks = plan.iter_blocks;
     e.k0 = k0;
     e.K = iters + (loss_hist ? 1 : 0);
     e.iters = iters;
