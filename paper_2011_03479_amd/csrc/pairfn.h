@@ -163,13 +163,41 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
     return ok;
 }
 
-// The non-edge value every sweep and edge correction of d <= 16 uses: the table for tau
-// from its bottom up, else (per lane) the closed form.  A deterministic function of r2, so the
-// sweep and the edge pass subtract exactly what the other added.
+// The same table staged as two float4 per segment, {n0 (int32 bits), r0, c1, c2} and
+// {c3, d1, d2, d3} with n0 + r0 = c0 (n0 integer) and d = slope_k (c1, 2 c2, 3 c3):
+//   dl = 2^n0 2^(r0 + f(c1 + f(c2 + f c3))),  d dl/d delta = dl (d1 + f(d2 + f d3)).
+// Two gathers instead of one, but fewer dependent operations after them; the fused
+// gradient-descent iteration, whose waves are few and short, runs faster with it (the long
+// sweeps, bound by LDS bank conflicts, with the one-gather form).
 template <bool W>
+__device__ __forceinline__ bool pair_nonedge_tab2(float r2, const PairParams &P, const float4 *__restrict__ tab,
+                                                  float tko, unsigned segs, float &dl, float &cc, float &w) {
+    float rinv = hw_rsq(r2);
+    float delta = r2 * rinv;
+    float tk = __builtin_fmaf(delta, P.tk_scale, tko);
+    float f = __builtin_amdgcn_fractf(tk);
+    const int k = floor_to_int(tk);
+    const bool ok = k >= 0;
+    const unsigned off = min((unsigned)k, segs) << 5;
+    const float4 *e = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(tab) + off);
+    const float4 A = e[0], B = e[1];
+    const float r = __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(B.x, f, A.w), f, A.z), f, A.y);
+    const float D = __builtin_fmaf(__builtin_fmaf(B.w, f, B.z), f, B.y);
+    dl = __builtin_amdgcn_ldexpf(hw_exp2(r), __float_as_int(A.x));
+    const float c1 = dl * D;  // d dl / d delta
+    cc = c1 * rinv;
+    if (W) w = c1 * __builtin_fmaf(0.34657359028f, c1, __builtin_fmaf(delta, P.tk_scale, P.tk_off) * P.wk2);
+    return ok;
+}
+
+// The non-edge value every sweep and edge correction of d <= 16 uses: the table for tau
+// from its bottom up, else (per lane) the closed form.  A deterministic function of r2 for
+// a given table form, so a sweep and its edge pass subtract exactly what the other added.
+template <bool W, bool TWO = false>
 __device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,
                                              float tko, unsigned segs, float &dl, float &cc, float &w) {
-    const bool ok = pair_nonedge_tab<W>(r2, P, tab, tko, segs, dl, cc, w);
+    const bool ok = TWO ? pair_nonedge_tab2<W>(r2, P, tab, tko, segs, dl, cc, w)
+                        : pair_nonedge_tab<W>(r2, P, tab, tko, segs, dl, cc, w);
     if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
         float dl2, cc2, w2;
         pair_eval_t<W>(r2, 1.0f, P, dl2, cc2, w2);

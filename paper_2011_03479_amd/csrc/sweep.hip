@@ -51,10 +51,21 @@ __device__ __forceinline__ void stage_ltab(float4 *dst) {
     for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) dst[q] = src[q];
 }
 
-template <bool W = false>
+// The two-float4 form (pair_nonedge_tab2) of the same table: 2 kLtabF4 float4.
+__device__ __forceinline__ void stage_ltab2(float4 *dst, float slope_k) {
+    const float4 *src = reinterpret_cast<const float4 *>(kLtab);
+    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) {
+        const float4 c = src[q];
+        const float n0 = rintf(c.x);
+        dst[2 * q] = make_float4(__int_as_float((int)n0), c.x - n0, c.y, c.z);
+        dst[2 * q + 1] = make_float4(c.w, slope_k * c.y, slope_k * (2.0f * c.z), slope_k * (3.0f * c.w));
+    }
+}
+
+template <bool W = false, bool TWO = false>
 __device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float tko, float &dl,
                                         float &cc, float &w) {
-    nonedge_eval<W>(r2, P, tab, tko, kLtabSegs, dl, cc, w);
+    nonedge_eval<W, TWO>(r2, P, tab, tko, kLtabSegs, dl, cc, w);
 }
 
 // What the per-vertex "extra" output of a sweep accumulates (the array called rowloss /
@@ -83,7 +94,7 @@ struct XView {
 // it holds the partial of column c_l(s-1) = c_{l-dir}(s), so rotating it by one lane
 // realigns it with c_l(s), and the rotation and this step's addition are one DPP add.
 // After the last step lane l holds the partial of column c_l(s1 - 1).
-template <int D, int R, bool MASK, int EX>
+template <int D, int R, bool MASK, int EX, bool TWO = false>
 __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
                                             float (&colacc)[D + (EX != 0 ? 1 : 0)], float (&gi)[R][D],
                                             float (&li)[R], float &loss, int lane, int dir, int col0, int n,
@@ -99,7 +110,7 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
             float diff[D];
             float r2 = sqdist_eps<D>(xi[r], xc, diff);
             float dl, cc, w = 0.0f;
-            nonedge<EX == kExZ>(r2, P, tab, tko, dl, cc, w);
+            nonedge<EX == kExZ, TWO>(r2, P, tab, tko, dl, cc, w);
             if (MASK) {
                 bool valid = (irow[r] < j) && (j < n);
                 dl = valid ? dl : 0.0f;
@@ -364,9 +375,9 @@ __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// Exact edge correction of one CSR entry (i, j): the gradient change (cc+ - cc-)(x_i - x_j)
-// of row i, and dl+ - dl- (the caller counts the loss for i < j only: each undirected edge
-// has two entries, each updating its own row).
+// Exact edge correction of one CSR entry (i, j) in the fused iteration (two-float4 table):
+// the gradient change (cc+ - cc-)(x_i - x_j) of row i, and dl+ - dl- (the caller counts the
+// loss for i < j only: each undirected edge has two entries, each updating its own row).
 // ------------------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float (&dg)[D], const PairParams &P,
@@ -380,7 +391,7 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
     float r2 = sqdist_eps<D>(xi, xj, diff);
     float dlp, ccp, dln, ccn, wn;
     pair_eval(r2, -1.0f, P, dlp, ccp);
-    nonedge(r2, P, tab, table_offset(P, kLtabZero), dln, ccn, wn);
+    nonedge<false, true>(r2, P, tab, table_offset(P, kLtabZero), dln, ccn, wn);
     const float dcc = ccp - ccn;
 #pragma unroll
     for (int k = 0; k < D; ++k) dg[k] = dcc * diff[k];
@@ -698,7 +709,7 @@ struct IterLds {
     float rowp[4][64 * D];  // per-wave partials: plain LDS stores, summed in wave order
     float colp[4][64 * D];
     float wl[4];
-    float4 tab[kLtabF4];
+    float4 tab[2 * kLtabF4];  // two-float4 table form
 };
 
 // Iteration k of one gradient-descent run, executed by workgroup b of the run's
@@ -731,7 +742,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
         if (b == a.units && k > 0 && a.loss_hist) reduce_loss(a, k - 1, sh);
         return;
     }
-    stage_ltab(L.tab);
+    stage_ltab2(L.tab, a.P.slope_k);
     __syncthreads();
     float loss = 0.0f;
     if (b < a.units_edge) {
@@ -779,11 +790,11 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
         }
         li[0] = 0.0f;
         if ((I == J) || (col0 + 64 > a.n))
-            sweep_steps<D, 1, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
-                                           a.P, L.tab);
+            sweep_steps<D, 1, true, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
+                                                 s0 + 16, a.P, L.tab);
         else
-            sweep_steps<D, 1, false, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0, s0 + 16,
-                                            a.P, L.tab);
+            sweep_steps<D, 1, false, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
+                                                  s0 + 16, a.P, L.tab);
         const int cl = (lane + dir * (s0 + 15)) & 63;  // column whose partial this lane holds
 #pragma unroll
         for (int q = 0; q < D; ++q) {
