@@ -1,16 +1,25 @@
 // Negative-sampled weighted majorization (Sec. III-C, Fig. nonedges, Fig. algo): O(m) work
 // per iteration instead of O(n^2).
 //
-// One lane per CSR entry (i, j) with i < j.  The lane evaluates the edge's parabola and draws
-// two non-edges: g for i and h for j, each with its own 32-bit LCG (s <- 1103515245 s + 1, the
-// generator of the paper), its state seeded from SplitMix64(seed + 2 e + side) so the draws
-// do not depend on how lanes are scheduled.  A draw maps the low 23 bits of s to a float f in
-// [1, 2) and takes floor(f n - n) in single precision (multiply, then subtract); it is
-// rejected when it is the vertex itself, outside [0, n) or adjacent to it - adjacency is a
-// probe of the exact edge hash, the per-sample use the hash was built for - and the LCG steps
-// again, at most max_tries draws.  Each of the (up to) three pairs adds its gradient term
-// c (x_a - x_b) and its parabola weight w = dl''/2 to both ends with atomics, and its dl to
-// the lane's loss; x <- x - g / (2 z) then applies Eq. 5 over that multiset of pairs.
+// The pairs of one step: every edge (i, j), i < j, once, and for each of its ends a sampled
+// non-edge - g for i and h for j - each drawn with its own 32-bit LCG (s <- 1103515245 s + 1,
+// the generator of the paper), its state seeded from SplitMix64(seed + 2 e + side), e the
+// CSR index of (i, j) with i < j and side 0 for i, 1 for j, so the draws do not depend on
+// how lanes are scheduled.  A draw maps the low 23 bits of s to a float f in [1, 2) and
+// takes floor(f n - n) in single precision (multiply, then subtract); it is rejected when it
+// is the vertex itself, outside [0, n) or adjacent to it - adjacency is a probe of the exact
+// edge hash, the per-sample use the hash was built for - and the LCG steps again, at most
+// max_tries draws.  Each pair adds its gradient term c (x_a - x_b) and its parabola weight
+// w = dl''/2 to both ends, and its dl to the loss; x <- x - g / (2 z) then applies Eq. 5
+// over that multiset of pairs.
+//
+// Layout: one lane per DIRECTED CSR entry (r, c), lanes in CSR order.  The lane adds the
+// edge's term for row r (the mirror entry (c, r) adds it for c; the edge's dl is counted by
+// the entry with r < c) and draws the sample of r that belongs to this edge end: side 0 and
+// e = its own index when r < c, else side 1 and e = the index of (c, r) in row c (binary
+// search of the sorted row).  Both of r's terms are summed over the lanes of each row run
+// before one atomic per run (a wave covers a few rows); only the sample's far end g takes a
+// scattered atomic: about d + 1 per directed entry instead of 6 (d + 1) per edge.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,6 +27,7 @@
 
 #include "internal.h"
 #include "pairfn.h"
+#include "tiles.h"
 
 namespace gempe {
 namespace {
@@ -40,26 +50,19 @@ __device__ __forceinline__ int draw_non_neighbour(int v, int n, unsigned state, 
     return -1;
 }
 
-__device__ __forceinline__ float add_pair(const float *__restrict__ X, int d, int a, int b, float sign_a,
-                                          const PairParams &P, float *__restrict__ G, float *__restrict__ Z) {
-    float r2 = 0.0f;
-    for (int k = 0; k < d; ++k) {
-        const float df = X[(size_t)a * d + k] - X[(size_t)b * d + k];
-        r2 = __builtin_fmaf(df, df, r2);
+// Index of (c, r) in the sorted CSR row c (the edge is known to exist).
+__device__ __forceinline__ long long mirror_index(const int64_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col, int c, int r) {
+    long long lo = row_ptr[c], hi = row_ptr[c + 1];
+    while (lo < hi) {
+        const long long mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < r) lo = mid + 1; else hi = mid;
     }
-    float dl, cc, w;
-    pair_eval_t<true>(r2, sign_a, P, dl, cc, w);
-    for (int k = 0; k < d; ++k) {
-        const float t = cc * (X[(size_t)a * d + k] - X[(size_t)b * d + k]);
-        atomicAdd(&G[(size_t)a * d + k], t);
-        atomicAdd(&G[(size_t)b * d + k], -t);
-    }
-    atomicAdd(&Z[a], w);
-    atomicAdd(&Z[b], w);
-    return dl;
+    return lo;
 }
 
 __global__ __launch_bounds__(kSampledBlock) void k_sampled(const float *__restrict__ X, int n, int d,
+                                                            const int64_t *__restrict__ row_ptr,
                                                             const int32_t *__restrict__ coo_row,
                                                             const int32_t *__restrict__ col, long long nnz,
                                                             const unsigned long long *__restrict__ table,
@@ -69,29 +72,70 @@ __global__ __launch_bounds__(kSampledBlock) void k_sampled(const float *__restri
                                                             float *__restrict__ partials) {
     __shared__ float wsum[kSampledBlock / 64];
     const long long e = (long long)blockIdx.x * kSampledBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     float loss = 0.0f;
+    int r = -1, c = 0, g = -1;
+    float cce = 0.0f, we = 0.0f, ccs = 0.0f, ws = 0.0f;
     if (e < nnz) {
-        const int i = coo_row[e], j = col[e];
-        int gs = -1, hs = -1;
-        if (i < j) {
-            const unsigned s0 = (unsigned)(gempe_mix64(seed + 2ull * (unsigned long long)e + 0x9e3779b97f4a7c15ull) >> 32);
-            const unsigned s1 =
-                (unsigned)(gempe_mix64(seed + 2ull * (unsigned long long)e + 1ull + 0x9e3779b97f4a7c15ull) >> 32);
-            gs = draw_non_neighbour(i, n, s0, max_tries, table, cap);
-            hs = draw_non_neighbour(j, n, s1, max_tries, table, cap);
-            loss += add_pair(X, d, i, j, -1.0f, P, G, Z);
-            if (gs >= 0) loss += add_pair(X, d, i, gs, 1.0f, P, G, Z);
-            if (hs >= 0) loss += add_pair(X, d, j, hs, 1.0f, P, G, Z);
-        }
+        r = coo_row[e];
+        c = col[e];
+        const int side = r > c ? 1 : 0;
+        const long long ec = side ? mirror_index(row_ptr, col, c, r) : e;
+        const unsigned s0 = (unsigned)(gempe_mix64(seed + 2ull * (unsigned long long)ec + (unsigned long long)side +
+                                                   0x9e3779b97f4a7c15ull) >> 32);
+        g = draw_non_neighbour(r, n, s0, max_tries, table, cap);
         if (samples) {
-            samples[2 * e] = gs;
-            samples[2 * e + 1] = hs;
+            if (side) {
+                samples[2 * e] = -1;
+                samples[2 * e + 1] = -1;
+                samples[2 * ec + 1] = g;
+            } else {
+                samples[2 * e] = g;
+            }
+        }
+        const float *xr = X + (size_t)r * d;
+        const float *xc = X + (size_t)c * d;
+        float r2 = 0.0f;
+        for (int k = 0; k < d; ++k) {
+            const float df = xr[k] - xc[k];
+            r2 = __builtin_fmaf(df, df, r2);
+        }
+        float dl;
+        pair_eval_t<true>(r2, -1.0f, P, dl, cce, we);
+        if (r < c) loss += dl;
+        if (g >= 0) {
+            const float *xg = X + (size_t)g * d;
+            float r2s = 0.0f;
+            for (int k = 0; k < d; ++k) {
+                const float df = xr[k] - xg[k];
+                r2s = __builtin_fmaf(df, df, r2s);
+            }
+            pair_eval_t<true>(r2s, 1.0f, P, dl, ccs, ws);
+            loss += dl;
         }
     }
+    // row r: both terms summed over the run of r in this wave, one atomic per run; the
+    // sample's far end g: a scattered atomic
+    for (int k = 0; k < d; ++k) {
+        float vr = 0.0f, vg = 0.0f;
+        if (r >= 0) {
+            const float xk = X[(size_t)r * d + k];
+            vr = cce * (xk - X[(size_t)c * d + k]);
+            if (g >= 0) {
+                vg = ccs * (xk - X[(size_t)g * d + k]);
+                vr += vg;
+            }
+        }
+        if (seg_sum_to_head(r, lane, vr)) atomicAdd(&G[(size_t)r * d + k], vr);
+        if (g >= 0) atomicAdd(&G[(size_t)g * d + k], -vg);
+    }
+    float zr = (r >= 0) ? we + (g >= 0 ? ws : 0.0f) : 0.0f;
+    if (seg_sum_to_head(r, lane, zr)) atomicAdd(&Z[r], zr);
+    if (g >= 0) atomicAdd(&Z[g], ws);
     float v = loss;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+    if (lane == 0) wsum[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) partials[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
@@ -153,7 +197,8 @@ hipError_t gempe_launch_sampled_step(const gempe_graph_s *g, int d, float *X, un
         hipLaunchKernelGGL(k_sampled_zero, dim3(1), dim3(64), 0, s, reinterpret_cast<float *>(status), 1LL,
                            reinterpret_cast<float *>(status), 0);
     if (g->nnz > 0)
-        hipLaunchKernelGGL(k_sampled, dim3((unsigned)nb), dim3(kSampledBlock), 0, s, X, n, d, g->coo_row, g->col_idx,
+        hipLaunchKernelGGL(k_sampled, dim3((unsigned)nb), dim3(kSampledBlock), 0, s, X, n, d, g->row_ptr, g->coo_row,
+                           g->col_idx,
                            (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, seed, max_tries, P, G, Z,
                            samples, part);
     else

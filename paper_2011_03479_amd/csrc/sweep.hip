@@ -398,21 +398,6 @@ __device__ __forceinline__ float edge_entry(const XView &xv, int i, int j, float
     return dlp - dln;
 }
 
-// Lanes hold values keyed by a row id that is non-decreasing across the active lanes of the
-// wave (CSR order; inactive lanes carry key -1).  Sums each run of equal keys into its first
-// lane (segmented suffix sums, log2(64) shuffle steps) and returns true in those head
-// lanes, so a hub row costs one atomic per wave instead of one per entry.
-__device__ __forceinline__ bool seg_sum_to_head(int key, int lane, float &v) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int ko = __shfl_down(key, off, 64);
-        float vo = __shfl_down(v, off, 64);
-        if (lane + off < 64 && ko == key) v += vo;
-    }
-    int kp = __shfl_up(key, 1, 64);
-    return key >= 0 && (lane == 0 || kp != key);
-}
-
 constexpr int kEdgeBlock = 256;
 
 template <int EX>

@@ -1,6 +1,6 @@
-// Device helpers shared by the sweeps and the distance histogram: the upper-triangle tile
-// order, the XCD-aware workgroup mapping, the DPP wave rotation of the Latin-square
-// schedule, and the squared distance accumulated coordinate by coordinate.
+// Device helpers shared by the sweeps, the edge passes, the sampled step and the distance
+// histogram: the upper-triangle tile order, the XCD-aware workgroup mapping, the DPP wave
+// rotation of the Latin-square schedule, segmented row sums, and the squared distances.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,6 +48,21 @@ __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
+}
+
+// Lanes hold values keyed by a row id that is non-decreasing across the active lanes of the
+// wave (CSR order; inactive lanes carry key -1).  Sums each run of equal keys into its first
+// lane (segmented suffix sums, log2(64) shuffle steps) and returns true in those head
+// lanes, so a hub row costs one atomic per wave instead of one per entry.
+__device__ __forceinline__ bool seg_sum_to_head(int key, int lane, float &v) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int ko = __shfl_down(key, off, 64);
+        float vo = __shfl_down(v, off, 64);
+        if (lane + off < 64 && ko == key) v += vo;
+    }
+    int kp = __shfl_up(key, 1, 64);
+    return key >= 0 && (lane == 0 || kp != key);
 }
 
 // Sum over the 16 lanes of each DPP row, returned in all 16: rotations by 8 and 4 lanes, then
