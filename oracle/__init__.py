@@ -59,6 +59,10 @@ def _bind(path: str):
     lib.oracle_loss_grad.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
                                      ctypes.c_double, dp, dp, i64p, dp, dp]
     lib.oracle_loss_grad.restype = None
+    lib.oracle_loss_grad_shard.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double), dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_loss_grad_shard.restype = None
     u64p = ctypes.POINTER(ctypes.c_uint64)
     fp = ctypes.POINTER(ctypes.c_float)
     lib.oracle_histogram.argtypes = [ctypes.c_int, ctypes.c_int, fp, i64p, i32p, ctypes.c_int, ctypes.c_float,
@@ -153,6 +157,23 @@ def loss_grad(X, row_ptr, col_idx, mu: float = 1.5, sigma: float = 1.0, want_gra
     if want_abs_slope:
         out["abs_slope"] = AS
     return out
+
+
+def loss_grad_shard(X, row_ptr, col_idx, strip_rows: int, nshards: int, shard: int, mu: float = 1.5,
+                    sigma: float = 1.0):
+    """One shard of the pair sum (strips of strip_rows rows, strip q paired with S-1-q, pair p
+    owned by shard p mod nshards): {"loss", "grad", "edge_hits"} over the shard's pairs; FP64."""
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    loss = ctypes.c_double()
+    hits = ctypes.c_int64()
+    G = np.zeros((n, d), dtype=np.float64)
+    lib.oracle_loss_grad_shard(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
+                               float(mu), float(sigma), int(strip_rows), int(nshards), int(shard),
+                               ctypes.byref(loss), _ptr(G, ctypes.c_double), ctypes.byref(hits))
+    return {"loss": loss.value, "grad": G, "edge_hits": hits.value}
 
 
 def rows(X, row_ptr, col_idx, rows_idx, mu: float = 1.5, sigma: float = 1.0, wm=False):

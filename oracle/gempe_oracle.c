@@ -197,6 +197,63 @@ void oracle_loss_grad(int n, int d, const double *X, const int64_t *row_ptr,
     free(H);
 }
 
+/*
+ * One shard of the all-pairs sum (the split of the pair work over several devices; the paper
+ * splits its edge blocks over cores, Sec. III-A).  Pair i < j lies in strip floor(i /
+ * strip_rows); with S = ceil(n / strip_rows) strips, strips q and S - 1 - q form strip pair
+ * min(q, S - 1 - q), and shard s of G owns the strip pairs p with p mod G == s.
+ *   loss      : sum of dl(i, j) over the shard's pairs i < j (rows in index order)
+ *   grad      : n x d, row v sums the gradient terms of the shard's pairs that contain v
+ *   edge_hits : edges among the shard's pairs
+ */
+static int shard_owns(int i, int j, int strip_rows, int S, int G, int s) {
+    int lo = i < j ? i : j;
+    int q = lo / strip_rows;
+    int p = q < S - 1 - q ? q : S - 1 - q;
+    return p % G == s;
+}
+
+void oracle_loss_grad_shard(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
+                            double mu, double sigma, int strip_rows, int nshards, int shard, double *loss,
+                            double *grad, int64_t *edge_hits) {
+    const int S = (n + strip_rows - 1) / strip_rows;
+    double *U = (double *)calloc((size_t)n, sizeof(double));
+    int64_t *H = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+#pragma omp parallel
+    {
+        unsigned char *flag = (unsigned char *)calloc((size_t)n, 1);
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < n; ++i) {
+            const double *xi = X + (size_t)i * d;
+            mark_row(row_ptr, col_idx, i, flag, 1);
+            for (int j = 0; j < n; ++j) {
+                if (j == i || !shard_owns(i, j, strip_rows, S, nshards, shard)) continue;
+                const double *xj = X + (size_t)j * d;
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) r2 += (xi[k] - xj[k]) * (xi[k] - xj[k]);
+                double delta = sqrt(r2), dl, d1, d2;
+                oracle_pair(delta, flag[j] != 0, mu, sigma, &dl, &d1, &d2);
+                if (j > i) {
+                    U[i] += dl;
+                    H[i] += flag[j] != 0;
+                }
+                double c = (delta > 0.0) ? d1 / delta : 0.0;
+                if (grad)
+                    for (int k = 0; k < d; ++k) grad[(size_t)i * d + k] += c * (xi[k] - xj[k]);
+            }
+            mark_row(row_ptr, col_idx, i, flag, 0);
+        }
+        free(flag);
+    }
+    double total = 0.0;
+    int64_t hits = 0;
+    for (int i = 0; i < n; ++i) total += U[i], hits += H[i];
+    if (loss) *loss = total;
+    if (edge_hits) *edge_hits = hits;
+    free(U);
+    free(H);
+}
+
 /* Threads OpenMP will use (for reporting). */
 int oracle_num_threads(void) {
 #ifdef _OPENMP

@@ -425,6 +425,32 @@ def pin_sampled_step():
     assert close(loss, L, 1e-12)
 
 
+def pin_shard_partition():
+    """The shard split of the pair sum: the shards partition the pairs (their losses, gradients
+    and edge hits add up to the whole; one shard is the whole), and shard s holds exactly the
+    pairs whose smaller vertex lies in strip s or S-1-s when every shard has one strip pair
+    (checked against the per-row upper-triangle losses of the row oracle)."""
+    n, T = 150, 16
+    g = synth.chung_lu(n, 6.0, 2.5, seed=3)
+    X = synth.init_embedding(n, 3, seed=4)
+    full = oracle.loss_grad(X, g.row_ptr, g.col_idx)
+    scale = float(np.abs(full["grad"]).max())
+    one = oracle.loss_grad_shard(X, g.row_ptr, g.col_idx, T, 1, 0)
+    assert close(one["loss"], full["loss"], 1e-14) and one["edge_hits"] == full["edge_hits"]
+    assert np.allclose(one["grad"], full["grad"], rtol=0, atol=1e-12 * scale)
+    for G in (2, 3, 5):
+        parts = [oracle.loss_grad_shard(X, g.row_ptr, g.col_idx, T, G, s) for s in range(G)]
+        assert close(sum(p["loss"] for p in parts), full["loss"], 1e-12)
+        assert sum(p["edge_hits"] for p in parts) == full["edge_hits"]
+        assert np.allclose(sum(p["grad"] for p in parts), full["grad"], rtol=0, atol=1e-12 * scale)
+    S = (n + T - 1) // T                                  # 10 strips: 5 strip pairs
+    upper = oracle.rows(X, g.row_ptr, g.col_idx, np.arange(n))["upper_loss"]
+    strip = np.array([upper[q * T:(q + 1) * T].sum() for q in range(S)])
+    for s in range(S // 2):
+        part = oracle.loss_grad_shard(X, g.row_ptr, g.col_idx, T, S // 2, s)
+        assert close(part["loss"], strip[s] + strip[S - 1 - s], 1e-12), s
+
+
 ALL_PINS = [
     pin_pair_vs_mpmath,
     pin_pair_vs_scipy,
@@ -441,4 +467,5 @@ ALL_PINS = [
     pin_sigma_histogram_converges,
     pin_sampler,
     pin_sampled_step,
+    pin_shard_partition,
 ]

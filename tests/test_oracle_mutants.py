@@ -37,6 +37,9 @@ MUTANTS = {
     "sample_side_swapped": ("samples[2 * e + 1] = draw_non_neighbour(j, n, s1,", "samples[2 * e + 1] = draw_non_neighbour(i, n, s1,"),
     "sampled_edge_as_non_edge": ("add_pair(d, X, i, j, 1, mu, sigma, Y, Z, &loss);", "add_pair(d, X, i, j, 0, mu, sigma, Y, Z, &loss);"),
     "bisection_direction": ("if (Fn(s, ctx) < 0.0) lo = s; else hi = s;", "if (Fn(s, ctx) < 0.0) hi = s; else lo = s;"),
+    "shard_by_larger_vertex": ("int lo = i < j ? i : j;", "int lo = i < j ? j : i;"),
+    "shard_strips_unpaired": ("int p = q < S - 1 - q ? q : S - 1 - q;", "int p = q;"),
+    "shard_owner_shifted": ("return p % G == s;", "return (p + 1) % G == s;"),
 }
 
 
