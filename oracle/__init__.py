@@ -63,6 +63,9 @@ def _bind(path: str):
                                            ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_double), dp, ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_loss_grad_shard.restype = None
+    lib.oracle_rows_shard.argtypes = [ctypes.c_int, ctypes.c_int, dp, i64p, i32p, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64p, dp]
+    lib.oracle_rows_shard.restype = None
     u64p = ctypes.POINTER(ctypes.c_uint64)
     fp = ctypes.POINTER(ctypes.c_float)
     lib.oracle_histogram.argtypes = [ctypes.c_int, ctypes.c_int, fp, i64p, i32p, ctypes.c_int, ctypes.c_float,
@@ -174,6 +177,21 @@ def loss_grad_shard(X, row_ptr, col_idx, strip_rows: int, nshards: int, shard: i
                                float(mu), float(sigma), int(strip_rows), int(nshards), int(shard),
                                ctypes.byref(loss), _ptr(G, ctypes.c_double), ctypes.byref(hits))
     return {"loss": loss.value, "grad": G, "edge_hits": hits.value}
+
+
+def rows_shard(X, row_ptr, col_idx, rows_idx, strip_rows: int, nshards: int, shard: int, mu: float = 1.5,
+               sigma: float = 1.0):
+    """Gradient rows (r x d) of one shard (see loss_grad_shard) for a subset of rows; FP64."""
+    lib = _load()
+    Xd = np.ascontiguousarray(X, dtype=np.float64)
+    n, d = Xd.shape
+    rp, ci = _graph_arrays(row_ptr, col_idx)
+    ri = np.ascontiguousarray(rows_idx, dtype=np.int64)
+    G = np.zeros((ri.shape[0], d))
+    lib.oracle_rows_shard(n, d, _ptr(Xd, ctypes.c_double), _ptr(rp, ctypes.c_int64), _ptr(ci, ctypes.c_int32),
+                          float(mu), float(sigma), int(strip_rows), int(nshards), int(shard), int(ri.shape[0]),
+                          _ptr(ri, ctypes.c_int64), _ptr(G, ctypes.c_double))
+    return G
 
 
 def rows(X, row_ptr, col_idx, rows_idx, mu: float = 1.5, sigma: float = 1.0, wm=False):

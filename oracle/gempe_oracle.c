@@ -213,6 +213,36 @@ static int shard_owns(int i, int j, int strip_rows, int S, int G, int s) {
     return p % G == s;
 }
 
+/* The same shard for a list of rows only: grad (nrows x d) of rows[r] over the shard's pairs. */
+void oracle_rows_shard(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
+                       double mu, double sigma, int strip_rows, int nshards, int shard, int nrows,
+                       const int64_t *rows, double *grad) {
+    const int S = (n + strip_rows - 1) / strip_rows;
+#pragma omp parallel
+    {
+        unsigned char *flag = (unsigned char *)calloc((size_t)n, 1);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nrows; ++r) {
+            const int i = (int)rows[r];
+            const double *xi = X + (size_t)i * d;
+            mark_row(row_ptr, col_idx, i, flag, 1);
+            for (int k = 0; k < d; ++k) grad[(size_t)r * d + k] = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i || !shard_owns(i, j, strip_rows, S, nshards, shard)) continue;
+                const double *xj = X + (size_t)j * d;
+                double r2 = 0.0;
+                for (int k = 0; k < d; ++k) r2 += (xi[k] - xj[k]) * (xi[k] - xj[k]);
+                double delta = sqrt(r2), dl, d1, d2;
+                oracle_pair(delta, flag[j] != 0, mu, sigma, &dl, &d1, &d2);
+                double c = (delta > 0.0) ? d1 / delta : 0.0;
+                for (int k = 0; k < d; ++k) grad[(size_t)r * d + k] += c * (xi[k] - xj[k]);
+            }
+            mark_row(row_ptr, col_idx, i, flag, 0);
+        }
+        free(flag);
+    }
+}
+
 void oracle_loss_grad_shard(int n, int d, const double *X, const int64_t *row_ptr, const int32_t *col_idx,
                             double mu, double sigma, int strip_rows, int nshards, int shard, double *loss,
                             double *grad, int64_t *edge_hits) {

@@ -443,6 +443,10 @@ def pin_shard_partition():
         assert close(sum(p["loss"] for p in parts), full["loss"], 1e-12)
         assert sum(p["edge_hits"] for p in parts) == full["edge_hits"]
         assert np.allclose(sum(p["grad"] for p in parts), full["grad"], rtol=0, atol=1e-12 * scale)
+    sub = np.array([0, 15, 16, 77, 149])
+    part = oracle.loss_grad_shard(X, g.row_ptr, g.col_idx, T, 3, 1)
+    assert np.allclose(oracle.rows_shard(X, g.row_ptr, g.col_idx, sub, T, 3, 1), part["grad"][sub], rtol=1e-13,
+                       atol=1e-14 * scale)
     S = (n + T - 1) // T                                  # 10 strips: 5 strip pairs
     upper = oracle.rows(X, g.row_ptr, g.col_idx, np.arange(n))["upper_loss"]
     strip = np.array([upper[q * T:(q + 1) * T].sum() for q in range(S)])
