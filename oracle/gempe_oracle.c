@@ -234,8 +234,8 @@ void oracle_rows_shard(int n, int d, const double *X, const int64_t *row_ptr, co
                 for (int k = 0; k < d; ++k) r2 += (xi[k] - xj[k]) * (xi[k] - xj[k]);
                 double delta = sqrt(r2), dl, d1, d2;
                 oracle_pair(delta, flag[j] != 0, mu, sigma, &dl, &d1, &d2);
-                double c = (delta > 0.0) ? d1 / delta : 0.0;
-                for (int k = 0; k < d; ++k) grad[(size_t)r * d + k] += c * (xi[k] - xj[k]);
+                double cs = (delta > 0.0) ? d1 / delta : 0.0;
+                for (int k = 0; k < d; ++k) grad[(size_t)r * d + k] += cs * (xi[k] - xj[k]);
             }
             mark_row(row_ptr, col_idx, i, flag, 0);
         }
@@ -263,13 +263,13 @@ void oracle_loss_grad_shard(int n, int d, const double *X, const int64_t *row_pt
                 for (int k = 0; k < d; ++k) r2 += (xi[k] - xj[k]) * (xi[k] - xj[k]);
                 double delta = sqrt(r2), dl, d1, d2;
                 oracle_pair(delta, flag[j] != 0, mu, sigma, &dl, &d1, &d2);
-                if (j > i) {
+                if (i < j) {
                     U[i] += dl;
                     H[i] += flag[j] != 0;
                 }
-                double c = (delta > 0.0) ? d1 / delta : 0.0;
+                double cs = (delta > 0.0) ? d1 / delta : 0.0;
                 if (grad)
-                    for (int k = 0; k < d; ++k) grad[(size_t)i * d + k] += c * (xi[k] - xj[k]);
+                    for (int k = 0; k < d; ++k) grad[(size_t)i * d + k] += cs * (xi[k] - xj[k]);
             }
             mark_row(row_ptr, col_idx, i, flag, 0);
         }
