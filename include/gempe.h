@@ -132,6 +132,27 @@ gempe_status gempe_loss_grad(gempe_graph g, int32_t d, const float *X, float *gr
                              const gempe_params *p, hipStream_t stream);
 
 /*
+ * One device's share of gempe_loss_grad when the all-pairs sweep is split over several
+ * devices (the block-wise division of the pair work, Sec. III-A, across devices instead of
+ * cores; Eq. 2 summed over a subset of the pairs).  The upper triangle is cut into strips of
+ * R = gempe_shard_rows(g, d, p) rows (pair i < j lies in strip floor(i / R)); with S strips,
+ * strips q and S-1-q form strip pair min(q, S-1-q), and shard `shard` of `nshards` owns the
+ * strip pairs p with p mod nshards == shard (equal pair counts up to one strip pair).
+ *   grad, loss, edge_hits : as gempe_loss_grad, summed over the shard's pairs only; the
+ *                           sums over all shards give gempe_loss_grad's values (to FP32
+ *                           rounding; edge hits exactly)
+ * FP32 only (GEMPE_ERR_UNSUPPORTED for BF16_GRAM); 0 <= shard < nshards.  Same workspace as
+ * gempe_loss_grad.  Asynchronous.
+ */
+gempe_status gempe_loss_grad_shard(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
+                                   int64_t *edge_hits, int32_t shard, int32_t nshards, void *ws,
+                                   size_t ws_bytes, const gempe_params *p, hipStream_t stream);
+
+/* The strip height R of gempe_loss_grad_shard's split for this graph, d and parameters
+ * (0 on invalid arguments or BF16_GRAM). [host] */
+int64_t gempe_shard_rows(gempe_graph g, int32_t d, const gempe_params *p);
+
+/*
  * One fixed-step gradient-descent step X <- X - eta * grad DL(X), in place.
  *   loss_before : float64[1] or NULL, receives DL at the X on entry
  * eta > 0 and finite.  Asynchronous.

@@ -115,6 +115,41 @@ extern "C" gempe_status gempe_loss_grad(gempe_graph g, int32_t d, const float *X
     return GEMPE_OK;
 }
 
+extern "C" int64_t gempe_shard_rows(gempe_graph g, int32_t d, const gempe_params *p) {
+    if (check_common(g, d, p, "shard_rows") != GEMPE_OK) return 0;
+    if (p->precision != GEMPE_FP32) {
+        gempe_fail(GEMPE_ERR_UNSUPPORTED, "shard_rows: shards are FP32 only");
+        return 0;
+    }
+    return gempe_make_plan(g, d, false).T;
+}
+
+extern "C" gempe_status gempe_loss_grad_shard(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
+                                              int64_t *edge_hits, int32_t shard, int32_t nshards, void *ws,
+                                              size_t ws_bytes, const gempe_params *p, hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "loss_grad_shard");
+    if (st != GEMPE_OK) return st;
+    if (p->precision != GEMPE_FP32)
+        return gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_shard: shards are FP32 only");
+    if (!X || !loss) return gempe_fail(GEMPE_ERR_ARG, "loss_grad_shard: X and loss are required");
+    if (nshards < 1 || shard < 0 || shard >= nshards)
+        return gempe_fail(GEMPE_ERR_ARG, "loss_grad_shard: need 0 <= shard < nshards");
+    SweepPlan plan = gempe_make_plan(g, d, false);
+    WsLayout L = gempe_ws_layout(g, d, plan);
+    if ((st = check_ws(g, d, ws, ws_bytes, L, "loss_grad_shard")) != GEMPE_OK) return st;
+    plan.shard = shard;
+    plan.nshards = nshards;
+    plan.items = gempe_shard_items(plan.nt, shard, nshards);
+    plan.grid = std::max<long long>(1, (plan.items + 7) / 8) * 8;  // whole rounds over the 8 XCDs
+    plan.partials = plan.items + plan.edge_blocks;
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    float *G = grad ? grad : reinterpret_cast<float *>(w + L.gbuf);
+    GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, G, nullptr, reinterpret_cast<float *>(w + L.partials),
+                                         w + L.counters, loss, edge_hits, gempe_pair_params(p), stream, true,
+                                         gempe_gram_ctx(L, w, p), reinterpret_cast<double *>(w + L.red)));
+    return GEMPE_OK;
+}
+
 extern "C" gempe_status gempe_step(gempe_graph g, int32_t d, float *X, float eta, double *loss_before, void *ws,
                                    size_t ws_bytes, const gempe_params *p, hipStream_t stream) {
     gempe_status st = check_common(g, d, p, "step");

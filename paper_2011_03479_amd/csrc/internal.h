@@ -114,7 +114,13 @@ struct SweepPlan {
     // BF16 Gram screen (precision GEMPE_BF16_GRAM): items = 64x64 upper tiles, D = padded
     // dimension of the exact pass over the flagged tiles
     bool bf16 = false;
+    // one shard of the upper triangle (FP32 sweeps): items are then that shard's tiles
+    int shard = 0, nshards = 1;
 };
+
+// Tiles of shard s of G over nt strips (strips p and nt-1-p paired, pair p owned by shard
+// p mod G); nt (nt + 1) / 2 when G == 1.
+long long gempe_shard_items(int nt, int s, int G);
 
 struct WsLayout {
     size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, ...

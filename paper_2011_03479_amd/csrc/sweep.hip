@@ -144,7 +144,8 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
                                                         int nt, long long items, long long per_xcd,
                                                         float *__restrict__ G,
                                                         float *__restrict__ rowloss,
-                                                        float *__restrict__ partials, PairParams P) {
+                                                        float *__restrict__ partials, PairParams P, int shard,
+                                                        int nshards) {
     constexpr int T = 64 * R * W;
     constexpr int NC = D + (EX != 0 ? 1 : 0);
     __shared__ float cs[W > 1 ? W * 64 * NC : 1];  // per-wave column partials
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
     stage_ltab(ltab);
     __syncthreads();
     int I, J;
-    tile_of(t, nt, I, J);
+    item_tile(t, nt, shard, nshards, I, J);
     const int dir = rot_dir(lane);
 
     const int row0 = I * T + wave * 64 * R;
@@ -345,12 +346,13 @@ template <int D, int EX>
 __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, int n, int d, int nt,
                                                    long long items, long long per_xcd,
                                                    float *__restrict__ G, float *__restrict__ rowloss,
-                                                   float *__restrict__ partials, PairParams P) {
+                                                   float *__restrict__ partials, PairParams P, int shard,
+                                                   int nshards) {
     extern __shared__ float lds[];
     const long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;
     int I, J;
-    tile_of(t, nt, I, J);
+    item_tile(t, nt, shard, nshards, I, J);
     float l = wide_tile<D, EX, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
     if (threadIdx.x == 0) partials[t] = l;
 }
@@ -408,7 +410,8 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
                                                       unsigned long long cap, float *__restrict__ G,
                                                       float *__restrict__ rowloss,
                                                       float *__restrict__ partials,
-                                                      unsigned long long *hits, PairParams P) {
+                                                      unsigned long long *hits, PairParams P,
+                                                      int strip_rows, int nt, int shard, int nshards) {
     __shared__ float wsum[kEdgeBlock / 64];
     __shared__ unsigned whit[kEdgeBlock / 64];
     __shared__ float4 ltab[kLtabF4];
@@ -432,10 +435,13 @@ __global__ __launch_bounds__(kEdgeBlock) void k_edges(const float *__restrict__ 
         float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
         pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
         nonedge<EX == kExZ>(r2, P, ltab, table_offset(P, kLtabZero), dln, ccn, wn);
-        dcc = ccp - ccn;
-        ddl = dlp - dln;
-        dw = wp - wn;
-        if (i < j) {
+        // a shard corrects only the edges of its own tiles (the entry keeps its row key, so
+        // the row runs stay contiguous, and adds nothing)
+        const bool own = nshards <= 1 || strip_owned(min(i, j) / strip_rows, nt, shard, nshards);
+        dcc = own ? ccp - ccn : 0.0f;
+        ddl = own ? dlp - dln : 0.0f;
+        dw = own ? wp - wn : 0.0f;
+        if (i < j && own) {
             dloss = ddl;
             hit = hits && gempe_hash_contains(table, cap, gempe_edge_key(i, j)) ? 1u : 0u;
         }
@@ -481,7 +487,8 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
                                                     const unsigned long long *__restrict__ table,
                                                     unsigned long long cap, float *__restrict__ G,
                                                     float *__restrict__ rowloss, float *__restrict__ partials,
-                                                    unsigned long long *hits, PairParams P) {
+                                                    unsigned long long *hits, PairParams P, int strip_rows,
+                                                    int nt, int shard, int nshards) {
     constexpr int C = D / 16;
     __shared__ float wsum[4];
     __shared__ unsigned whit[4];
@@ -505,8 +512,10 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
             const int jl = lane < cnt ? col[base + lane] : i;
             for (int c0 = 0; c0 < cnt; c0 += 4) {
                 const int k = c0 + grp;
-                const bool valid = k < cnt;
                 const int j = __shfl(jl, k & 63, 64);
+                // a shard corrects only the edges of its own tiles
+                const bool valid =
+                    k < cnt && (nshards <= 1 || strip_owned(min(i, j) / strip_rows, nt, shard, nshards));
                 float df[C];
                 const float r2 = group16_sqdist<C>(xr, X + (size_t)(valid ? j : i) * d, sub, d, df);
                 float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
@@ -916,6 +925,13 @@ constexpr int kRed1Blocks = 1024;  // first level of the FP64 loss reduction  //
 
 }  // namespace
 
+long long gempe_shard_items(int nt, int s, int G) {
+    if (G <= 1) return (long long)nt * (nt + 1) / 2;
+    long long c = 0;
+    for (int p = s; p <= nt - 1 - p; p += G) c += (p == nt - 1 - p) ? (long long)(nt - p) : (long long)nt + 1;
+    return c;
+}
+
 SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
     SweepPlan p;
     if (bf16) {
@@ -1059,7 +1075,7 @@ void launch_small(const SweepPlan &pl, hipStream_t s, const float *X, int n, int
                   float *part, PairParams P) {
     long long per = pl.grid / kXcd;
     hipLaunchKernelGGL((k_sweep_small<D, R, W, EX>), dim3((unsigned)pl.grid), dim3(64 * W), 0, s, X, n, d,
-                       pl.nt, pl.items, per, G, rl, part, P);
+                       pl.nt, pl.items, per, G, rl, part, P, pl.shard, pl.nshards);
 }
 
 template <int D, int EX>
@@ -1086,7 +1102,7 @@ void launch_wide(const SweepPlan &pl, hipStream_t s, const float *X, int n, int 
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sweep_wide<D, EX>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
-                       pl.items, per, G, rl, part, P);
+                       pl.items, per, G, rl, part, P, pl.shard, pl.nshards);
 }
 
 template <int D, int EX>
@@ -1160,7 +1176,8 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
         // wide: one wave per CSR row (also writes the partial of rows without edges)
 #define GEMPE_EDGES_ROWS(DD)                                                                              \
     hipLaunchKernelGGL((k_edges_rows<DD, EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr, \
-                       g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, hits, P)
+                       g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, hits, P,    \
+                       plan.T, plan.nt, plan.shard, plan.nshards)
         if (plan.D == 32)
             GEMPE_EDGES_ROWS(32);
         else if (plan.D == 64)
@@ -1171,7 +1188,7 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     } else if (g->nnz > 0) {
         hipLaunchKernelGGL((k_edges<EX>), dim3(plan.edge_blocks), dim3(kEdgeBlock), 0, s, X, d, g->coo_row,
                            g->col_idx, (long long)g->nnz, g->hash, (unsigned long long)g->hash_cap, grad, extra,
-                           epart, hits, P);
+                           epart, hits, P, plan.T, plan.nt, plan.shard, plan.nshards);
     } else {
         hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, epart, (long long)plan.edge_blocks, nullptr, 0LL,
                            nullptr, 0);

@@ -22,6 +22,36 @@ __device__ inline void tile_of(long long t, int nt, int &I, int &J) {
     J = (int)(i + (t - start(i)));
 }
 
+// Sharding of the upper triangle over several devices: strips p and nt-1-p (of rows p T and
+// (nt-1-p) T, T the plan's tile edge) form strip pair min(p, nt-1-p), nt + 1 tiles together
+// (the middle strip of an odd nt alone has nt - p); shard s of G owns the pairs p with
+// p mod G == s, so every shard gets about the same number of pairs.
+__device__ inline bool strip_owned(int I, int nt, int s, int G) {
+    const int p = min(I, nt - 1 - I);
+    return p % G == s;
+}
+
+// Tile (I, J) of item t: all upper-triangle tiles when G == 1 (tile_of), else the t-th tile
+// of shard s (its strip pairs in increasing order, strip p's tiles first).
+__device__ inline void item_tile(long long t, int nt, int s, int G, int &I, int &J) {
+    if (G <= 1) {
+        tile_of(t, nt, I, J);
+        return;
+    }
+    const long long per = (long long)nt + 1;
+    const long long q = t / per;
+    const int p = s + (int)q * G;
+    const int off = (int)(t - q * per);
+    const int first = nt - p;  // tiles of strip p
+    if (off < first) {
+        I = p;
+        J = p + off;
+    } else {
+        I = nt - 1 - p;
+        J = I + (off - first);
+    }
+}
+
 // Workgroup b -> tile index such that the workgroups one XCD receives (b = x, x+8, ...)
 // take consecutive tiles (same row strip: x_I stays in that XCD's L2).
 __device__ inline long long xcd_item(long long b, long long per_xcd) {

@@ -38,6 +38,8 @@ ABI_SYMBOLS = (
     "gempe_has_edge",
     "gempe_workspace_bytes",
     "gempe_loss_grad",
+    "gempe_loss_grad_shard",
+    "gempe_shard_rows",
     "gempe_step",
     "gempe_embed",
     "gempe_status_string",
@@ -158,6 +160,11 @@ def load(path: str | None = None):
     lib.gempe_workspace_bytes.restype = ctypes.c_size_t
     lib.gempe_loss_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, P, vp]
     lib.gempe_loss_grad.restype = st
+    lib.gempe_loss_grad_shard.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
+                                          ctypes.c_size_t, P, vp]
+    lib.gempe_loss_grad_shard.restype = st
+    lib.gempe_shard_rows.argtypes = [vp, ctypes.c_int32, P]
+    lib.gempe_shard_rows.restype = ctypes.c_int64
     lib.gempe_step.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_float, vp, vp, ctypes.c_size_t, P, vp]
     lib.gempe_step.restype = st
     lib.gempe_embed.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_float, vp, vp,
@@ -346,6 +353,31 @@ def loss_grad(g: Graph, X, ws=None, params=None, want_grad=True, want_hits=True,
         )
     _check(load().gempe_loss_grad(g.handle, int(d), _ptr(X), _ptr(out.grad), _ptr(out.loss), _ptr(out.edge_hits),
                                   _ptr(out.row_loss), _ptr(ws), int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return out
+
+
+def shard_rows(g: Graph, d: int, params=None) -> int:
+    """Strip height of the shard split (gempe_shard_rows)."""
+    p = params or params_default()
+    return int(load().gempe_shard_rows(g.handle, int(d), ctypes.byref(p)))
+
+
+def loss_grad_shard(g: Graph, X, shard: int, nshards: int, ws=None, params=None, want_grad=True, stream=None):
+    """One shard's share of the loss, gradient and edge hits (gempe_loss_grad_shard)."""
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    if ws is None:
+        ws = workspace(g, d, p)
+    out = LossGrad(
+        loss=torch.empty(1, dtype=torch.float64, device="cuda"),
+        grad=torch.empty((n, d), dtype=torch.float32, device="cuda") if want_grad else None,
+        edge_hits=torch.empty(1, dtype=torch.int64, device="cuda"),
+        row_loss=None,
+    )
+    _check(load().gempe_loss_grad_shard(g.handle, int(d), _ptr(X), _ptr(out.grad), _ptr(out.loss),
+                                        _ptr(out.edge_hits), int(shard), int(nshards), _ptr(ws), int(ws.numel()),
+                                        ctypes.byref(p), _stream(stream)))
     return out
 
 
