@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 #include "pairfn.h"
@@ -174,97 +175,156 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
             nha[a][r] = ig < n ? -(0.5f * nrm[ig]) : -INFINITY;
         }
     const float sI = R64 < nb64 ? smax128[R64 / 2] : 0.0f;
-    // the 64 x 64 sub-tile of column tile Jt held in LDS buffer cur
-    auto screen_tile = [&](int Jt, int cur) {
-        const long long C64 = (long long)Jt * CW + wc;  // this wave's sub-tile column
-        if (R64 <= C64 && C64 < nb64) {
-            floatx16 acc[2][2] = {{nha[0], nha[0]}, {nha[1], nha[1]}};
-            const __bf16 *Bc = Bs[cur];
+    // Per step a wave computes its 64 x 64 sub-tile of column tile Jt (LDS buffer cur) into
+    // acc and reads the columns' thresholds from LDS (the buffer is refilled after the next
+    // barrier); the epilogue reduces acc to the sub-tile's flag.  The first four waves run
+    // the epilogue right after their MFMAs, the last four run it at the start of the next
+    // step, before their MFMAs: the two waves that share a SIMD then reduce while the other
+    // one multiplies, instead of both leaving the matrix core idle at the same time.
+    // (wave w runs on SIMD w % 4; the 128-row strips of the widest rows keep one order, the
+    // second copy of the loop would not fit in the registers)
+    constexpr bool kDesync = RW == 8 || D <= 80;
+    const bool late = kDesync && wave >= 4;
+    // acc = G~ - n~_i/2 over the sub-tile (R64, Jt * CW + wc), B fragments from LDS buffer cur
+    auto mma_tile = [&](int cur, floatx16 (&acc)[2][2]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int kk = 0; kk < D / 16; ++kk) {
-                bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + lrow) * S + kk * 16 + lk);
-                bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + 32 + lrow) * S + kk * 16 + lk);
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b1, acc[1][1], 0, 0, 0);
-            }
-            // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block,
-            // holding G~ - n~_i/2; near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>
-            // delta~^2 < theta^2, taken on the lane's largest value (one compare per column);
-            // theta carries the 2^-7 (|x_i| + |x_j|) margin of the two 128-vertex blocks
-            const bool diag = (R64 == C64);
-            bool near = false;
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int jl = wc * 64 + b * 32 + (lane & 31);
-                const int jg = Jt * TC + jl;
-                const float th = theta0 + 0.0078125f * (sI + hS[cur][jl]);
-                const float hb = jg < n ? 0.5f * hN[cur][jl] - 0.5f * th * th : INFINITY;
-                float m = -INFINITY;
-                if (diag) {  // only pairs i < j of a diagonal sub-tile
+            for (int b = 0; b < 2; ++b) acc[a][b] = nha[a];
+        const __bf16 *Bc = Bs[cur];
 #pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int ig = (int)R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-                            m = fmaxf(m, ig < jg ? acc[a][b][r] : -INFINITY);
-                        }
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r]);
-                }
-                near = near || (m > hb);
-            }
-            const bool any = __ballot(near) != 0ull;
-            if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
+        for (int kk = 0; kk < D / 16; ++kk) {
+            bf16x8 b0 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + lrow) * S + kk * 16 + lk);
+            bf16x8 b1 = *reinterpret_cast<const bf16x8 *>(Bc + (wc * 64 + 32 + lrow) * S + kk * 16 + lk);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][0], b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[kk][1], b1, acc[1][1], 0, 0, 0);
         }
     };
+    // near test G~ - n~_i/2 > n~_j/2 - theta^2/2  <=>  delta~^2 < theta^2, where theta
+    // carries the 2^-7 (|x_i| + |x_j|) margin of the two 128-vertex blocks: the right side
+    // for this lane's column of half b of the sub-tile column
+    auto threshold = [&](int Jt, int cur, int b) __attribute__((always_inline)) {
+        const int jl = wc * 64 + b * 32 + (lane & 31);
+        const float th = theta0 + 0.0078125f * (sI + hS[cur][jl]);
+        return Jt * TC + jl < n ? 0.5f * hN[cur][jl] - 0.5f * th * th : INFINITY;
+    };
+    // flag of sub-tile (R64, C64) of column tile Jt from its accumulators
+    auto epilogue = [&](const floatx16 (&acc)[2][2], long long C64, int Jt, auto hb_of) __attribute__((always_inline)) {
+        // accumulator r of lane l: row (r/4)*8 + (l/32)*4 + r%4, column l%32 of the block,
+        // holding G~ - n~_i/2; the test is taken on the lane's largest value (one compare
+        // per column)
+        const bool diag = (R64 == C64);
+        bool near = false;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int jg = Jt * TC + wc * 64 + b * 32 + (lane & 31);
+            float m = -INFINITY;
+            if (diag) {  // only pairs i < j of a diagonal sub-tile
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int ig = (int)R64 * 64 + a * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+                        m = fmaxf(m, ig < jg ? acc[a][b][r] : -INFINITY);
+                    }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) m = fmaxf(m, acc[a][b][r]);
+            }
+            near = near || (m > hb_of(b));
+        }
+        const bool any = __ballot(near) != 0ull;
+        if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
+    };
+    // the late waves' sub-tile held over to the next step, with its thresholds (its LDS
+    // buffer is refilled after the next barrier)
+    floatx16 hacc[2][2];
+    float hb[2];
+    long long hC64 = -1;  // -1: none
+    int hJ = 0;
+    auto held_epilogue = [&]() __attribute__((always_inline)) {
+        if (hC64 >= 0) epilogue(hacc, hC64, hJ, [&](int b) { return hb[b]; });
+        hC64 = -1;
+    };
+    // the step loop, compiled once per wave group so that each copy keeps only the
+    // registers its own order needs
+    auto run = [&](auto late_tag) __attribute__((always_inline)) {
+        constexpr bool kLate = decltype(late_tag)::value;
+        auto screen_tile = [&](int Jt, int cur) __attribute__((always_inline)) {
+            const long long C64 = (long long)Jt * CW + wc;  // this wave's sub-tile column
+            const bool live = R64 <= C64 && C64 < nb64;
+            if constexpr (kLate) {
+                held_epilogue();
+                if (live) {
+                    mma_tile(cur, hacc);
+                    hb[0] = threshold(Jt, cur, 0);
+                    hb[1] = threshold(Jt, cur, 1);
+                    hC64 = C64;
+                    hJ = Jt;
+                }
+            } else if (live) {
+                floatx16 acc[2][2];
+                mma_tile(cur, acc);
+                epilogue(acc, C64, Jt, [&](int b) { return threshold(Jt, cur, b); });
+            }
+        };
 
-    if constexpr (PER <= 2) {
-        // global loads two steps ahead (two staging register sets): a load has a whole step
-        // of MFMAs more to arrive before its commit
-        bf16x8 ra[PER], rb[PER];
-        stage(J, ra);
-        commit(J, 0, ra);
-        if (J + Q < ntile) stage(J + Q, ra);
-        __syncthreads();
-        for (;;) {
-            // tile J in buffer 0, tile J + Q arriving in ra
-            if (J + 2 * Q < ntile) stage(J + 2 * Q, rb);
-            screen_tile(J, 0);
-            if (J + Q < ntile) commit(J + Q, 1, ra);
+        if constexpr (PER <= 2) {
+            // global loads two steps ahead (two staging register sets): a load has a whole step
+            // of MFMAs more to arrive before its commit
+            bf16x8 ra[PER], rb[PER];
+            stage(J, ra);
+            commit(J, 0, ra);
+            if (J + Q < ntile) stage(J + Q, ra);
             __syncthreads();
-            J += Q;
-            if (J >= ntile) break;
-            // tile J in buffer 1, tile J + Q arriving in rb
-            if (J + 2 * Q < ntile) stage(J + 2 * Q, ra);
-            screen_tile(J, 1);
-            if (J + Q < ntile) commit(J + Q, 0, rb);
+            for (;;) {
+                // tile J in buffer 0, tile J + Q arriving in ra
+                if (J + 2 * Q < ntile) stage(J + 2 * Q, rb);
+                screen_tile(J, 0);
+                if (J + Q < ntile) commit(J + Q, 1, ra);
+                __syncthreads();
+                J += Q;
+                if (J >= ntile) break;
+                // tile J in buffer 1, tile J + Q arriving in rb
+                if (J + 2 * Q < ntile) stage(J + 2 * Q, ra);
+                screen_tile(J, 1);
+                if (J + Q < ntile) commit(J + Q, 0, rb);
+                __syncthreads();
+                J += Q;
+                if (J >= ntile) break;
+            }
+        } else {
+            {
+                bf16x8 regs[PER];
+                stage(J, regs);
+                commit(J, 0, regs);
+            }
             __syncthreads();
-            J += Q;
-            if (J >= ntile) break;
+            for (int it = 0; J < ntile; ++it, J += Q) {
+                const int cur = it & 1;
+                const int Jn = J + Q;
+                bf16x8 regs[PER];
+                if (Jn < ntile) stage(Jn, regs);
+                screen_tile(J, cur);
+                // buffer cur ^ 1 was last read in the previous step, which every wave finished
+                // before that step's closing barrier: commit into it without waiting
+                if (Jn < ntile) commit(Jn, cur ^ 1, regs);
+                __syncthreads();
+            }
         }
+        if constexpr (kLate) held_epilogue();  // the last sub-tile
+    };
+    if constexpr (kDesync) {
+        if (late)
+            run(std::true_type{});
+        else
+            run(std::false_type{});
     } else {
-        {
-            bf16x8 regs[PER];
-            stage(J, regs);
-            commit(J, 0, regs);
-        }
-        __syncthreads();
-        for (int it = 0; J < ntile; ++it, J += Q) {
-            const int cur = it & 1;
-            const int Jn = J + Q;
-            bf16x8 regs[PER];
-            if (Jn < ntile) stage(Jn, regs);
-            screen_tile(J, cur);
-            // buffer cur ^ 1 was last read in the previous step, which every wave finished
-            // before that step's closing barrier: commit into it without waiting
-            if (Jn < ntile) commit(Jn, cur ^ 1, regs);
-            __syncthreads();
-        }
+        run(std::false_type{});
     }
 }
 
