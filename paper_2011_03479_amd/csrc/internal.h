@@ -150,6 +150,7 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 struct PairParamsHost {
     float mu_s, inv_sigma, c_neg, c_pos;  // see gempe::PairParams
     float tk_scale, tk_off, slope_k, r_scale, w_scale, wk2;
+    int table_full;
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 

@@ -39,6 +39,8 @@ struct PairParams {
     float r_scale;    // -sigma ln 2          (R = phi/Phi from the slope term)
     float w_scale;    // 1 / (2 sigma^2 ln 2) (w = dl''/2 = R (R + tau) w_scale)
     float wk2;        // -1 / (32 sigma)      (table form of w, see pair_nonedge_tab)
+    int table_full;   // 1 when every non-edge tau >= -mu/sigma lies inside the table
+                      // (16 mu / sigma <= 127), so the sweeps need no below-table fallback
 };
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -193,12 +195,14 @@ __device__ __forceinline__ bool pair_nonedge_tab2(float r2, const PairParams &P,
 // The non-edge value every sweep and edge correction of d <= 16 uses: the table for tau
 // from its bottom up, else (per lane) the closed form.  A deterministic function of r2 for
 // a given table form, so a sweep and its edge pass subtract exactly what the other added.
-template <bool W, bool TWO = false>
+// CHK = false: the caller knows that no tau lies below the table (P.table_full), and the
+// per-pair test and its branch go, which lets the gathers of several pairs issue together.
+template <bool W, bool TWO = false, bool CHK = true>
 __device__ __forceinline__ void nonedge_eval(float r2, const PairParams &P, const float4 *__restrict__ tab,
                                              float tko, unsigned segs, float &dl, float &cc, float &w) {
     const bool ok = TWO ? pair_nonedge_tab2<W>(r2, P, tab, tko, segs, dl, cc, w)
                         : pair_nonedge_tab<W>(r2, P, tab, tko, segs, dl, cc, w);
-    if (__builtin_expect(__ballot(!ok) != 0ull, 0)) {
+    if (CHK && __builtin_expect(__ballot(!ok) != 0ull, 0)) {
         float dl2, cc2, w2;
         pair_eval_t<W>(r2, 1.0f, P, dl2, cc2, w2);
         dl = ok ? dl : dl2;

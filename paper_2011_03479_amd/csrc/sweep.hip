@@ -62,10 +62,15 @@ __device__ __forceinline__ void stage_ltab2(float4 *dst, float slope_k) {
     }
 }
 
-template <bool W = false, bool TWO = false>
+// The long sweeps drop the below-table test (P.table_full) only from this dimension up:
+// at d = 2 the version with the test measured faster (the test's branch is never taken,
+// and the compiler schedules that loop better), at d = 16 the version without it.
+constexpr int kNoChkMinD = 8;
+
+template <bool W = false, bool TWO = false, bool CHK = true>
 __device__ __forceinline__ void nonedge(float r2, const PairParams &P, const float4 *tab, float tko, float &dl,
                                         float &cc, float &w) {
-    nonedge_eval<W, TWO>(r2, P, tab, tko, kLtabSegs, dl, cc, w);
+    nonedge_eval<W, TWO, CHK>(r2, P, tab, tko, kLtabSegs, dl, cc, w);
 }
 
 // What the per-vertex "extra" output of a sweep accumulates (the array called rowloss /
@@ -94,7 +99,8 @@ struct XView {
 // it holds the partial of column c_l(s-1) = c_{l-dir}(s), so rotating it by one lane
 // realigns it with c_l(s), and the rotation and this step's addition are one DPP add.
 // After the last step lane l holds the partial of column c_l(s1 - 1).
-template <int D, int R, bool MASK, int EX, bool TWO = false>
+// CHK: test each pair for tau below the table (may be false when P.table_full).
+template <int D, int R, bool MASK, int EX, bool TWO = false, bool CHK = true>
 __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (&irow)[R], float (&xc)[D],
                                             float (&colacc)[D + (EX != 0 ? 1 : 0)], float (&gi)[R][D],
                                             float (&li)[R], float &loss, int lane, int dir, int col0, int n,
@@ -110,7 +116,7 @@ __device__ __forceinline__ void sweep_steps(const float (&xi)[R][D], const int (
             float diff[D];
             float r2 = sqdist_eps<D>(xi[r], xc, diff);
             float dl, cc, w = 0.0f;
-            nonedge<EX == kExZ, TWO>(r2, P, tab, tko, dl, cc, w);
+            nonedge<EX == kExZ, TWO, CHK>(r2, P, tab, tko, dl, cc, w);
             if (MASK) {
                 bool valid = (irow[r] < j) && (j < n);
                 dl = valid ? dl : 0.0f;
@@ -200,12 +206,21 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
             const int jc = c0 + lane;
 #pragma unroll
             for (int k = 0; k < D; ++k) xc[k] = (jc < n && k < d) ? X[(size_t)jc * d + k] : 0.0f;
-            if (masked)
-                sweep_steps<D, R, true, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+            if (D >= kNoChkMinD && P.table_full) {
+                if (masked)
+                    sweep_steps<D, R, true, EX, false, false>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n,
+                                                              0, 64, P, ltab);
+                else
+                    sweep_steps<D, R, false, EX, false, false>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0,
+                                                               n, 0, 64, P, ltab);
+            } else {
+                if (masked)
+                    sweep_steps<D, R, true, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
+                                                ltab);
+                else
+                    sweep_steps<D, R, false, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
                                                  ltab);
-            else
-                sweep_steps<D, R, false, EX>(xi, irow, xc, colacc, bg, bl, blk, lane, dir, c0, n, 0, 64, P,
-                                                  ltab);
+            }
         }
         // lane l now holds the partial of column c_l(63)
         const int jc = c0 + ((lane + 63 * dir) & 63);
@@ -783,12 +798,22 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
             colacc[q] = 0.0f;
         }
         li[0] = 0.0f;
-        if ((I == J) || (col0 + 64 > a.n))
-            sweep_steps<D, 1, true, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
-                                                 s0 + 16, a.P, L.tab);
-        else
-            sweep_steps<D, 1, false, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n, s0,
-                                                  s0 + 16, a.P, L.tab);
+        const bool msk = (I == J) || (col0 + 64 > a.n);
+        if (a.P.table_full) {
+            if (msk)
+                sweep_steps<D, 1, true, false, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0,
+                                                            a.n, s0, s0 + 16, a.P, L.tab);
+            else
+                sweep_steps<D, 1, false, false, true, false>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0,
+                                                             a.n, s0, s0 + 16, a.P, L.tab);
+        } else {
+            if (msk)
+                sweep_steps<D, 1, true, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n,
+                                                     s0, s0 + 16, a.P, L.tab);
+            else
+                sweep_steps<D, 1, false, false, true>(xi, irow, xc, colacc, gi, li, loss, lane, dir, col0, a.n,
+                                                      s0, s0 + 16, a.P, L.tab);
+        }
         const int cl = (lane + dir * (s0 + 15)) & 63;  // column whose partial this lane holds
 #pragma unroll
         for (int q = 0; q < D; ++q) {
@@ -896,8 +921,8 @@ using namespace gempe;
 
 namespace {
 PairParams dev_params(const PairParamsHost &h) {
-    return PairParams{h.mu_s,     h.inv_sigma, h.c_neg,   h.c_pos, h.tk_scale,
-                      h.tk_off,   h.slope_k,   h.r_scale, h.w_scale, h.wk2};
+    return PairParams{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
+                      h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full};
 }
 }  // namespace
 
@@ -1065,6 +1090,10 @@ PairParamsHost gempe_pair_params(const gempe_params *p) {
     h.r_scale = (float)(-p->sigma * 0.69314718055994530942);
     h.w_scale = (float)(1.0 / (2.0 * p->sigma * p->sigma * 0.69314718055994530942));
     h.wk2 = (float)(-1.0 / (32.0 * p->sigma));
+    // A non-edge has tau = (delta - mu) / sigma >= -mu / sigma; its table index
+    // 16 tau - 16 GEMPE_LTAB_LO is then at least 1 when 16 mu / sigma <= 16 (-LO) - 1, a
+    // margin of one segment over the FP32 rounding of the index arithmetic.
+    h.table_full = (GEMPE_LTAB_INV_H * p->mu / p->sigma <= -GEMPE_LTAB_LO * GEMPE_LTAB_INV_H - 1.0) ? 1 : 0;
     return h;
 }
 
