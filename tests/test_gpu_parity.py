@@ -78,6 +78,67 @@ def test_parameters_and_regimes(mu, sigma, scale):
     check_full(g, G, X, mu=mu, sigma=sigma, params=p, what=f"mu{mu} s{sigma} x{scale}")
 
 
+# The sweeps tabulate the non-edge term for tau >= -8 only.  With sigma < mu / 8 a close
+# non-edge pair falls below the table and is evaluated in closed form behind a per-pair
+# test; with the default slope every non-edge lies inside the table and the sweeps drop
+# that test.  Both forms, on the small-n and the multi-wave tile plans and in the fused
+# iteration.
+def _below_table_pairs(X, mu, sigma):
+    """Pairs i < j closer than mu - 8 sigma (counted on the CPU, in FP64)."""
+    Xd = X.astype(np.float64)
+    r2 = np.sum((Xd[:, None, :] - Xd[None, :, :]) ** 2, axis=-1)
+    return int(np.count_nonzero(np.triu(np.sqrt(r2) < mu - 8.0 * sigma, 1)))
+
+
+@pytest.mark.parametrize("n,d,scale", [(400, 2, 1.0), (300, 16, 0.05), (600, 8, 0.08)])
+def test_below_table_pairs(n, d, scale):
+    mu, sigma = 1.5, 0.15
+    g = synth.erdos_renyi(n, 8.0, seed=n + d)
+    X = (synth.init_embedding(n, d, 21 + d).astype(np.float64) * scale).astype(np.float32)
+    below = _below_table_pairs(X, mu, sigma)
+    assert below > 100, below
+    note(f"below-table parity n={n} d={d} pairs below the table: {below}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    check_full(g, G, X, mu=mu, sigma=sigma, params=gempe.params_default(mu=mu, sigma=sigma),
+               what=f"below-table n{n} d{d}")
+
+
+@pytest.mark.parametrize("sigma", [1.0, 0.15])
+def test_multiwave_plan_both_table_forms(sigma):
+    """n = 40,000 at d = 16 selects tiles of 2 rows per lane and 4 waves; contracted points
+    put most non-edges near, and below the table when sigma = 0.15."""
+    mu, n, d = 1.5, 40000, 16
+    g = synth.chung_lu(n, 12.0, 2.3, seed=77)
+    X = (synth.init_embedding(n, d, seed=78).astype(np.float64) * 0.05).astype(np.float32)
+    rng = np.random.default_rng(79)
+    rows = np.unique(np.concatenate([rng.choice(n, 60, replace=False), np.argsort(-np.diff(g.row_ptr))[:4]]))
+    if sigma < mu / 8:
+        assert _below_table_pairs(X[:400], mu, sigma) > 100
+    note(f"multi-wave plan n={n} d={d} sigma={sigma}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    check_rows(g, G, X, rows, mu=mu, sigma=sigma, params=gempe.params_default(mu=mu, sigma=sigma),
+               what=f"n{n} d{d} sigma{sigma}")
+
+
+def test_fused_iteration_below_table():
+    mu, sigma, n, d, iters = 1.5, 0.15, 1000, 2, 4
+    g = synth.chung_lu(n, 8.0, 2.5, seed=31)
+    X0 = synth.init_embedding(n, d, seed=32)
+    assert _below_table_pairs(X0, mu, sigma) > 100
+    eta = 0.01 / (n - 1)
+    p = gempe.params_default(mu=mu, sigma=sigma)
+    note(f"fused iteration below the table n={n} iters={iters}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    Xa = to_dev(X0)
+    h = torch.empty(iters + 1, dtype=torch.float64, device="cuda")
+    gempe.embed(G, Xa, iters, eta, params=p, loss_hist=h)
+    torch.cuda.synchronize()
+    ref_hist, X_ref = oracle.gd_trajectory(X0, g.row_ptr, g.col_idx, iters, eta, mu=mu, sigma=sigma)
+    assert np.allclose(h.cpu().numpy(), ref_hist, rtol=1e-5, atol=0)
+    xa = Xa.double().cpu().numpy()
+    assert np.max(np.linalg.norm(xa - X_ref, axis=1)) <= 1e-4 * np.max(np.linalg.norm(X_ref, axis=1))
+
+
 def test_two_vertices_and_coincident_points():
     note("two vertices / coincident points")
     X = np.array([[0.0, 0.0], [3.0, 4.0]], dtype=np.float32)
