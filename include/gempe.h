@@ -65,6 +65,12 @@ typedef enum gempe_precision {
 
 /* Flags (gempe_params.flags). */
 #define GEMPE_F_NONE 0u
+/* A schedule perturbation, for determinism tests: the FP32 sweeps (d <= 128, the fused
+ * gradient-descent iteration included) take their tiles in reverse order.  Every tile
+ * still writes its loss partial to its own slot and the FP64 sum runs in slot order, so
+ * the loss is bitwise the same as without the flag; the gradient differs only by the
+ * order of its FP32 atomic additions.  Ignored by the BF16 Gram path. */
+#define GEMPE_F_REVERSE_TILES 1u
 
 typedef struct gempe_params {
     double mu;          /* sigmoid position; the paper fixes mu = 1.5 (Sec. III-F)         */
@@ -72,7 +78,7 @@ typedef struct gempe_params {
     int32_t precision;  /* gempe_precision                                                  */
     int32_t reserved0;  /* must be 0                                                        */
     double near_k;      /* BF16_GRAM only: exact-recompute cut-off in sigmas (default 9)    */
-    uint32_t flags;     /* GEMPE_F_* (currently none)                                       */
+    uint32_t flags;     /* GEMPE_F_* (0 or GEMPE_F_REVERSE_TILES); other bits: GEMPE_ERR_ARG */
     uint32_t reserved1; /* must be 0                                                        */
 } gempe_params;
 

@@ -52,8 +52,10 @@ gempe_status gempe_check_problem(int32_t n, int32_t d, const gempe_params *p, co
     if (d < 1 || d > 128) return gempe_fail(GEMPE_ERR_ARG, w + ": d must be in [1, 128]");
     if (!(std::isfinite(p->mu) && std::isfinite(p->sigma) && p->sigma > 0.0))
         return gempe_fail(GEMPE_ERR_ARG, w + ": mu must be finite and sigma finite and > 0");
-    if (p->reserved0 != 0 || p->reserved1 != 0 || p->flags != GEMPE_F_NONE)
-        return gempe_fail(GEMPE_ERR_ARG, w + ": reserved fields and flags must be 0");
+    if (p->reserved0 != 0 || p->reserved1 != 0)
+        return gempe_fail(GEMPE_ERR_ARG, w + ": reserved fields must be 0");
+    if ((p->flags & ~GEMPE_F_REVERSE_TILES) != 0u)
+        return gempe_fail(GEMPE_ERR_ARG, w + ": unknown flag bits");
     if (p->precision == GEMPE_BF16_GRAM) {
         if (d < 16 || d % 16 != 0)
             return gempe_fail(GEMPE_ERR_ARG, w + ": BF16_GRAM needs d >= 16 and d % 16 == 0");

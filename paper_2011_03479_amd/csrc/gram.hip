@@ -628,7 +628,7 @@ hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X
                                    const PairParamsHost &h, int ex, float *G, float *extra, float *partials,
                                    hipStream_t s) {
     const gempe::PairParams P{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
-                              h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full};
+                              h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full, 0};
     if (ex == 2)
         launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s);
     else if (ex == 1)

@@ -151,6 +151,7 @@ struct PairParamsHost {
     float mu_s, inv_sigma, c_neg, c_pos;  // see gempe::PairParams
     float tk_scale, tk_off, slope_k, r_scale, w_scale, wk2;
     int table_full;
+    int reverse;  // GEMPE_F_REVERSE_TILES: the FP32 sweeps take their tiles in reverse order
 };
 PairParamsHost gempe_pair_params(const gempe_params *p);
 

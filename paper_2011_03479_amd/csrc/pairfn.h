@@ -41,6 +41,8 @@ struct PairParams {
     float wk2;        // -1 / (32 sigma)      (table form of w, see pair_nonedge_tab)
     int table_full;   // 1 when every non-edge tau >= -mu/sigma lies inside the table
                       // (16 mu / sigma <= 127), so the sweeps need no below-table fallback
+    int reverse;      // 1: the FP32 sweeps take their tiles in reverse order (a schedule
+                      // perturbation; each tile keeps its own loss-partial slot)
 };
 
 constexpr float kLog2e = 1.4426950408889634f;

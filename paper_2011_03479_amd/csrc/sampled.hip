@@ -190,7 +190,7 @@ hipError_t gempe_launch_sampled_step(const gempe_graph_s *g, int d, float *X, un
     unsigned *status = reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(part) +
                                                     align256(sizeof(float) * (size_t)nb));
     const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,
-                       pph.tk_off, pph.slope_k,   pph.r_scale, pph.w_scale, pph.wk2, pph.table_full};
+                       pph.tk_off, pph.slope_k,   pph.r_scale, pph.w_scale, pph.wk2, pph.table_full, 0};
     const long long zn = std::max<long long>(nd, n);
     hipLaunchKernelGGL(k_sampled_zero, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, s, G, nd, Z, n);
     if (clear_status)

@@ -160,8 +160,9 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long t = xcd_item(blockIdx.x, per_xcd);
+    long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
+    if (P.reverse) t = items - 1 - t;
     stage_ltab(ltab);
     __syncthreads();
     int I, J;
@@ -364,8 +365,9 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
                                                    float *__restrict__ partials, PairParams P, int shard,
                                                    int nshards) {
     extern __shared__ float lds[];
-    const long long t = xcd_item(blockIdx.x, per_xcd);
+    long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;
+    if (P.reverse) t = items - 1 - t;
     int I, J;
     item_tile(t, nt, shard, nshards, I, J);
     float l = wide_tile<D, EX, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
@@ -754,6 +756,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     stage_ltab2(L.tab, a.P.slope_k);
     __syncthreads();
     float loss = 0.0f;
+    int slot = b;
     if (b < a.units_edge) {
         // edge workgroups come first: their dependent gathers overlap the tiles
         const long long e0 = ((long long)b * 4 + wave) * a.epu;
@@ -781,7 +784,8 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
         // one 64 x 64 tile per workgroup; wave w runs steps [16 w, 16 w + 16) of the
         // schedule, the four waves' row and column partials meet in LDS
         const int dir = rot_dir(lane);
-        const int t = b - (int)a.units_edge;
+        const int t = a.P.reverse ? (int)(a.units - 1 - b) : b - (int)a.units_edge;
+        slot = (int)a.units_edge + t;  // the loss partial of tile t, whichever workgroup runs it
         int I, J;
         tile_of(t, a.nb, I, J);
         const int i = I * 64 + lane;
@@ -839,7 +843,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     loss = wave_sum(loss);
     if (lane == 0) wl[wave] = loss;
     __syncthreads();
-    if (threadIdx.x == 0) Pk[b] = (wl[0] + wl[1]) + (wl[2] + wl[3]);
+    if (threadIdx.x == 0) Pk[slot] = (wl[0] + wl[1]) + (wl[2] + wl[3]);
 }
 
 template <int D>
@@ -922,7 +926,7 @@ using namespace gempe;
 namespace {
 PairParams dev_params(const PairParamsHost &h) {
     return PairParams{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
-                      h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full};
+                      h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full, h.reverse};
 }
 }  // namespace
 
@@ -1094,6 +1098,7 @@ PairParamsHost gempe_pair_params(const gempe_params *p) {
     // 16 tau - 16 GEMPE_LTAB_LO is then at least 1 when 16 mu / sigma <= 16 (-LO) - 1, a
     // margin of one segment over the FP32 rounding of the index arithmetic.
     h.table_full = (GEMPE_LTAB_INV_H * p->mu / p->sigma <= -GEMPE_LTAB_LO * GEMPE_LTAB_INV_H - 1.0) ? 1 : 0;
+    h.reverse = (p->flags & GEMPE_F_REVERSE_TILES) ? 1 : 0;
     return h;
 }
 

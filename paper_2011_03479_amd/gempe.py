@@ -28,6 +28,9 @@ GEMPE_ERR_TIMEOUT = -7
 GEMPE_FP32 = 0
 GEMPE_BF16_GRAM = 1
 
+GEMPE_F_NONE = 0
+GEMPE_F_REVERSE_TILES = 1  # FP32 sweeps take their tiles in reverse order
+
 # Every symbol include/gempe.h declares (checked by the tests).
 ABI_SYMBOLS = (
     "gempe_params_default",

@@ -60,6 +60,14 @@ def test_host_side_argument_checks(lib):
         gempe.GEMPE_ERR_ARG
     assert lib.gempe_embed(None, 2, None, 1, ctypes.c_float(0.1), None, None, 0, ctypes.byref(p), None) == \
         gempe.GEMPE_ERR_ARG
+    # flags: GEMPE_F_REVERSE_TILES is the only known bit (the footprint query runs the
+    # problem checks on the host and answers 0 for a rejected problem)
+    pf = gempe.params_default(flags=gempe.GEMPE_F_REVERSE_TILES)
+    assert lib.gempe_job_footprint(1000, 10000, 2, 10, ctypes.byref(pf)) > 0
+    for bad in (2, 0x80000000):
+        pf = gempe.params_default(flags=bad)
+        assert lib.gempe_job_footprint(1000, 10000, 2, 10, ctypes.byref(pf)) == 0
+        assert "flag" in gempe.last_error()
     assert lib.gempe_graph_num_edges(None) == -1 and lib.gempe_graph_num_vertices(None) == -1
     assert lib.gempe_graph_destroy(None) == gempe.GEMPE_ERR_ARG
 

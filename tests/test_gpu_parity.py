@@ -217,6 +217,44 @@ def test_loss_is_deterministic_and_grad_stable():
         assert_grad_close(o["grad"], outs[0]["grad"], A, rtol=1e-5, what="run-to-run")
 
 
+@pytest.mark.parametrize("n,d", [(2500, 2), (1000, 16), (700, 32), (3000, 4)])
+def test_reversed_tile_order(n, d):
+    """Schedule perturbation: the sweep takes its tiles in reverse order (GEMPE_F_REVERSE_TILES).
+    Each tile keeps its loss-partial slot and the FP64 sum runs in slot order, so the loss is
+    bitwise unchanged; the gradient differs only by the order of its FP32 atomic additions."""
+    g = synth.chung_lu(n, min(10.0, (n - 1) / 3), 2.5, seed=5 * n + d)
+    X = synth.init_embedding(n, d, seed=n + 3 * d)
+    note(f"reversed tile order n={n} d={d}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    fwd = gpu_loss_grad(G, X)
+    rev = gpu_loss_grad(G, X, params=gempe.params_default(flags=gempe.GEMPE_F_REVERSE_TILES))
+    assert rev["loss"] == fwd["loss"], (rev["loss"], fwd["loss"])
+    assert rev["edge_hits"] == fwd["edge_hits"] == g.m
+    A = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_abs_slope=True)["abs_slope"]
+    assert_grad_close(rev["grad"], fwd["grad"], A, rtol=1e-5, what=f"reversed n{n} d{d}")
+
+
+def test_reversed_tile_order_fused_iteration():
+    """The fused gradient-descent iteration with its tiles in reverse order: the loss of the
+    start point is bitwise the same, the trajectory equal within the FP32 reassociation of the
+    gradient's atomic additions."""
+    n, d, iters = 3400, 2, 6
+    w = synth.workload("cl3400")
+    note(f"reversed tile order, fused iteration n={n} d={d} iters={iters}")
+    G = gempe.Graph(n, w.graph.row_ptr, w.graph.col_idx)
+    runs = []
+    for flags in (gempe.GEMPE_F_NONE, gempe.GEMPE_F_REVERSE_TILES):
+        X = to_dev(w.X0)
+        hist = torch.zeros(iters + 1, dtype=torch.float64, device="cuda")
+        gempe.embed(G, X, iters, w.eta, params=gempe.params_default(flags=flags), loss_hist=hist)
+        torch.cuda.synchronize()
+        runs.append((X.double().cpu().numpy(), hist.cpu().numpy()))
+    (xf, hf), (xr, hr) = runs
+    assert hr[0] == hf[0], (hr[0], hf[0])
+    np.testing.assert_allclose(hr, hf, rtol=1e-6)
+    assert np.max(np.abs(xr - xf)) <= 1e-5 * np.max(np.abs(xf))
+
+
 def test_workspace_and_argument_errors():
     g = synth.erdos_renyi(100, 5.0, seed=2)
     G = gempe.Graph(100, g.row_ptr, g.col_idx)
