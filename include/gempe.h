@@ -68,8 +68,9 @@ typedef enum gempe_precision {
 /* A schedule perturbation, for determinism tests: the FP32 sweeps (d <= 128, the fused
  * gradient-descent iteration included) take their tiles in reverse order.  Every tile
  * still writes its loss partial to its own slot and the FP64 sum runs in slot order, so
- * the loss is bitwise the same as without the flag; the gradient differs only by the
- * order of its FP32 atomic additions.  Ignored by the BF16 Gram path. */
+ * the loss at a given X is bitwise the same as without the flag; the gradient differs
+ * only by the order of its FP32 atomic additions (and the later iterates of gempe_embed by
+ * what that rounding carries forward).  Ignored by the BF16 Gram path. */
 #define GEMPE_F_REVERSE_TILES 1u
 
 typedef struct gempe_params {
