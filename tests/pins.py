@@ -240,6 +240,64 @@ def pin_edge_hits_and_rows():
     assert int(np.sum(np.diff(g.row_ptr)[sub])) >= int(rr["upper_hits"].sum())
 
 
+def pin_wm_parabola_two_vertices():
+    """The parabola of Sec. II-C (Eqs. 3-4) touches dl with the same slope and curvature at the
+    current distance.  On a two-vertex graph the oracle's z_0 is the pair's weight w and its
+    y_0 (Eq. 5) is w (x_1 + s (x_0 - x_1)); with x_0 = 0 and x_1 = (delta, 0) this gives
+    y_0 = w (delta - d).  The parabola p(t) = w (t - d)^2 + c has p' = 2 w (t - d) and p'' = 2 w,
+    so 2 y_0 must equal dl'(delta) and 2 z_0 must equal dl''(delta), both taken here from the
+    printed definition by high-precision differentiation.  A_0 is |dl'(delta)|."""
+    for mu, sigma in ((1.5, 1.0), (0.7, 1.7)):
+        for delta in (0.3, 1.0, 1.5, 2.2, 3.5, 6.0):
+            for edge in (True, False):
+                g = _graph_from_edges(2, [(0, 1)] if edge else [])
+                X = np.array([[0.0, 0.0], [delta, 0.0]])
+                r = oracle.rows(X, g.row_ptr, g.col_idx, np.array([0]), mu, sigma, wm=True)
+                _, rd1, rd2 = mp_dl_derivs(delta, edge, mu, sigma)
+                z0, y0 = float(r["z"][0]), r["y"][0]
+                assert close(2.0 * z0, rd2, 1e-8), (mu, sigma, delta, edge, 2 * z0, rd2)
+                assert close(2.0 * y0[0], rd1, 1e-8), (mu, sigma, delta, edge, 2 * y0[0], rd1)
+                assert abs(y0[1]) <= 1e-300
+                assert close(r["abs_slope"][0], abs(rd1), 1e-10), (delta, edge, r["abs_slope"][0], rd1)
+
+
+def pin_wm_brute_force_tiny():
+    """z_i, y_i (Eq. 5) and A_i = sum_j |dl'| on a 7-vertex graph against a pure-Python
+    brute force over all pairs with mpmath derivatives of the printed definition: each
+    pair's parabola weight is fixed by p'' = 2 w = dl'' and its target distance by
+    p'(delta) = 2 w (delta - d) = dl' (Sec. II-C, Eqs. 3-4)."""
+    rng = np.random.default_rng(8)
+    n, d = 7, 3
+    X = 0.8 * rng.standard_normal((n, d))
+    edges = [(0, 1), (1, 2), (2, 6), (3, 4), (0, 6), (4, 5)]
+    g = _graph_from_edges(n, edges)
+    E = set(edges) | {(b, a) for a, b in edges}
+    z = [mp.mpf(0)] * n
+    A = [mp.mpf(0)] * n
+    y = [[mp.mpf(0)] * d for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            xi = [mp.mpf(float(X[i, k])) for k in range(d)]
+            xj = [mp.mpf(float(X[j, k])) for k in range(d)]
+            delta = mp.sqrt(sum((a - b) ** 2 for a, b in zip(xi, xj)))
+            _, d1, d2 = mp_dl_derivs(delta, (i, j) in E)
+            w = d2 / 2
+            target = delta - d1 / (2 * w)
+            s = target / delta
+            z[i] += w
+            A[i] += abs(d1)
+            for k in range(d):
+                y[i][k] += w * (xj[k] + s * (xi[k] - xj[k]))
+    r = oracle.rows(X, g.row_ptr, g.col_idx, np.arange(n), wm=True)
+    for i in range(n):
+        assert close(r["z"][i], z[i], 1e-9), (i, r["z"][i], z[i])
+        assert close(r["abs_slope"][i], A[i], 1e-10), (i, r["abs_slope"][i], A[i])
+        yref = np.array([float(v) for v in y[i]])
+        assert np.allclose(r["y"][i], yref, rtol=1e-9, atol=1e-12 * float(z[i])), (i, r["y"][i], yref)
+
+
 def pin_wm_identity():
     """Eq. 5 with derivative-matched parabolas equals x_i - g_i / (2 z_i), z_i > 0."""
     rng = np.random.default_rng(31)
@@ -393,7 +451,8 @@ def pin_sampler():
 
 def pin_sampled_step():
     """The sampled step is Eq. 5 over the multiset {edges} + {sampled pairs}, written out here
-    with the pinned pair function; its loss is the dl summed over those pairs."""
+    with each pair's parabola fixed by the derivatives of the printed definition (mpmath);
+    its loss is the dl summed over those pairs."""
     g = synth.erdos_renyi(30, 4.0, seed=61)
     X = np.random.default_rng(62).standard_normal((30, 2))
     Xn, loss, smp = oracle.sampled_step(X, g.row_ptr, g.col_idx, 77, 32)
@@ -412,9 +471,9 @@ def pin_sampled_step():
     L = 0.0
     for a, b, edge in pairs:
         delta = float(np.linalg.norm(X[a] - X[b]))
-        dl, d1, d2 = oracle.pair(delta, edge)
-        w = d2 / 2
-        s_ab = (delta - d1 / (2 * w)) / delta
+        dl, d1, d2 = (float(v) for v in mp_dl_derivs(delta, edge))
+        w = d2 / 2                              # p'' = 2 w = dl''   (Eqs. 3-4)
+        s_ab = (delta - d1 / (2 * w)) / delta   # p'(delta) = 2 w (delta - d) = dl'
         Y[a] += w * (X[b] + s_ab * (X[a] - X[b]))
         Y[b] += w * (X[a] + s_ab * (X[b] - X[a]))
         Z[a] += w
@@ -455,8 +514,8 @@ def pin_shard_partition():
         assert close(part["loss"], strip[s] + strip[S - 1 - s], 1e-12), s
 
 
+# the slowest pin last: the mutant test stops at the first pin that rejects a mutant
 ALL_PINS = [
-    pin_pair_vs_mpmath,
     pin_pair_vs_scipy,
     pin_pair_closed_forms,
     pin_two_vertices,
@@ -466,10 +525,13 @@ ALL_PINS = [
     pin_invariances,
     pin_edge_hits_and_rows,
     pin_wm_identity,
+    pin_wm_parabola_two_vertices,
+    pin_wm_brute_force_tiny,
     pin_histogram_counts,
     pin_sigma_minimises_loss,
     pin_sigma_histogram_converges,
     pin_sampler,
     pin_sampled_step,
     pin_shard_partition,
+    pin_pair_vs_mpmath,
 ]

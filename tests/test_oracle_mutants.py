@@ -40,6 +40,10 @@ MUTANTS = {
     "shard_by_larger_vertex": ("int lo = i < j ? i : j;", "int lo = i < j ? j : i;"),
     "shard_strips_unpaired": ("int p = q < S - 1 - q ? q : S - 1 - q;", "int p = q;"),
     "shard_owner_shifted": ("return p % G == s;", "return (p + 1) % G == s;"),
+    "wm_weight_full_curvature": ("                    double w = 0.5 * d2;", "                    double w = d2;"),
+    "sampled_weight_full_curvature": ("\n    double w = 0.5 * d2;", "\n    double w = d2;"),
+    "abs_slope_scaled": ("A += fabs(d1);", "A += 100.0 * fabs(d1);"),
+    "abs_slope_over_distance": ("A += fabs(d1);", "A += fabs(d1) / delta;"),
 }
 
 
