@@ -1,13 +1,17 @@
 """Benchmark: all-pairs GEMPE gradient iterations on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cl3400]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cl1m]
 
-A step is one full iteration of the hot path: the all-pairs FP32 sweep (loss and gradient
-of every unordered vertex pair), the exact edge correction, the FP64 loss reduction and
-the update X <- X - eta G.  The default workload is the drawing-sized Chung-Lu graph
-(n = 3,400, about 19,000 edges, degree exponent 2.5, d = 2, 1,000 iterations).  Prints
-one JSON line with pairs/s (unordered pairs x iterations / time), the roofline figures of
-the dominant kernel and the FP64 CPU oracle timed on the host on a bounded sample.
+A step is one full iteration of the hot path: the all-pairs sweep (loss and gradient of
+every unordered vertex pair), the exact edge correction, the FP64 loss reduction with its
+finite check, and the update X <- X - eta G.  The default workload is the large all-pairs
+sweep: a Chung-Lu power-law graph with n = 1,000,000 vertices, mean degree 20 and degree
+exponent 2.3 (about 1e7 edges), d = 16, FP32; the same graph with the BF16 MFMA Gram screen
+is measured in the same run under `variants`, and the other workloads (the drawing-sized
+graph at d = 2, the SBM at d = 128 in BF16) under `extras`.  Prints one JSON line with
+pairs/s (unordered pairs x iterations / time), the roofline figures of the dominant
+kernel, timed with HIP events on the stream it runs on, the FP64 CPU oracle timed on the
+host on a bounded sample of rows, and the serving mix.
 """
 from __future__ import annotations
 
@@ -31,12 +35,16 @@ def flops_per_pair(d: int) -> int:
     return 7 * d + 31
 
 
+def traffic_path(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed PMC summary, or None
     when there is none or the kernel's sources changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_iter_cl3400_traffic.json")
+    path = traffic_path(workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -57,7 +65,7 @@ TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/
 
 
 def record_traffic(outdir: str, kernel: str, workload: str, copy_bytes: int):
-    """Writes profiles/k_iter_cl3400_traffic.json from four rocprofv3 --pmc runs under
+    """Writes profiles/traffic_<workload>.json from four rocprofv3 --pmc runs under
     `outdir` (pmc_fetch, pmc_write: FETCH_SIZE / WRITE_SIZE of the bench; pmc_copy_fetch,
     pmc_copy_write: the same counters over the --copy-probe copy of `copy_bytes` bytes).
     Each counter is the median over the kernel's dispatches; the copy fixes the factor that
@@ -89,7 +97,7 @@ def record_traffic(outdir: str, kernel: str, workload: str, copy_bytes: int):
            "fetch_factor": ff, "write_factor": wf,
            "fetch_bytes_per_launch": fetch * 1024 * ff, "write_bytes_per_launch": write * 1024 * wf,
            "traffic_bytes_per_launch": fetch * 1024 * ff + write * 1024 * wf}
-    out = os.path.join(ROOT, "profiles", "k_iter_cl3400_traffic.json")
+    out = traffic_path(workload)
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec))
 
@@ -178,27 +186,166 @@ def serving_bench(num_jobs: int, load: float, budget_gib: float, oracle_every: i
     }
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def gd_run(w, steps: int, warmup: int):
+    """`steps` gradient-descent iterations of workload `w` from its X0 after `warmup`
+    untimed ones, with the library's kernel timing on during the timed region.  Returns the
+    HIP-event time of the whole region and the per-class kernel times."""
+    import torch
+
+    from paper_2011_03479_amd import gempe
+
+    g = w.graph
+    n, d = g.n, w.d
+    stream = torch.cuda.current_stream()
+    params = gempe.params_default(precision=gempe.GEMPE_BF16_GRAM if w.precision == "bf16" else gempe.GEMPE_FP32)
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    ws = gempe.workspace(G, d, params)
+    X0 = torch.as_tensor(w.X0, device="cuda")
+    if warmup > 0:
+        gempe.embed(G, X0.clone(), warmup, w.eta, ws=ws, params=params)
+    X = X0.clone()
+    torch.cuda.synchronize()
+    for c in range(4):  # drop anything recorded before the timed region
+        gempe.timing_read(c)
+    gempe.timing_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    gempe.embed(G, X, steps, w.eta, ws=ws, params=params)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gempe.timing_enable(False)
+    ms = ev0.elapsed_time(ev1)
+    kern = {}
+    for c, name in ((gempe.GEMPE_TK_SWEEP, "sweep"), (gempe.GEMPE_TK_GRAM, "gram_screen"),
+                    (gempe.GEMPE_TK_EXACT, "exact_near"), (gempe.GEMPE_TK_EDGES, "edges")):
+        nl, kms = gempe.timing_read(c)
+        if nl:
+            kern[name] = {"launches": nl, "ms_total": kms, "ms_per_launch": kms / nl}
+    # the loss of the final iterate (one more evaluation, outside the timed region)
+    out = gempe.LossGrad(torch.empty(1, dtype=torch.float64, device="cuda"), None, None, None)
+    gempe.loss_grad(G, X, ws=ws, params=params, out=out)
+    torch.cuda.synchronize()
+    final_loss = float(out.loss.item())
+    G.close()
+    del ws, X, X0
+    torch.cuda.empty_cache()
+    N = n * (n - 1) // 2
+    return {"ms": ms, "wall_s": wall, "kernels": kern, "final_loss_bits": final_loss,
+            "value": N * steps / (ms / 1e3), "N": N}
+
+
+def roofline_of(w, r, steps: int):
+    """Roofline object of the dominant kernel: the FP32 sweep (7d + 31 flops per pair,
+    against the FP32 peak) or the BF16 Gram screen (2d MFMA flops per pair, against the BF16
+    peak), its per-launch time from the HIP events bracketing its launches."""
+    d, N = w.d, r["N"]
+    if w.precision == "bf16":
+        k = r["kernels"].get("gram_screen")
+        fpp, peak, bound, name = 2 * d, PEAK_BF16_TFLOPS, "mfma", "k_gram_screen (BF16 MFMA Gram screen)"
+    else:
+        k = r["kernels"].get("sweep")
+        fpp, peak, bound = flops_per_pair(d), PEAK_FP32_TFLOPS, "alu"
+        fused = w.graph.n <= 23000 and d <= 16
+        name = "k_iter (fused iteration: sweep, edge pass, update)" if fused else "k_sweep_small / k_sweep_wide"
+    if not k:
+        return None
+    kms = k["ms_per_launch"]
+    achieved = fpp * N / (kms / 1e3) / 1e12
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": name, "kernel_ms": kms, "kernel_launches": k["launches"],
+            "flops_per_pair": fpp, "timing": "HIP events around the kernel's launches on its stream"}
+
+
+def attach_traffic(roof, kernel: str, workload: str):
+    tr = measured_traffic(kernel, workload)
+    if roof is None or tr is None:
+        return
+    roof["traffic"] = tr["traffic_bytes_per_launch"]
+    roof["traffic_detail"] = {
+        "unit": "bytes per launch", "kernel": kernel, "fetch": tr["fetch_bytes_per_launch"],
+        "write": tr["write_bytes_per_launch"], "fetch_factor": tr["fetch_factor"], "write_factor": tr["write_factor"],
+        "source": f"profiles/traffic_{workload}.json (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)"}
+
+
+def summary(w, r, steps: int, warmup: int):
+    d = {"workload": w.name, "n": w.graph.n, "m": w.graph.m, "d": w.d, "precision": w.precision,
+         "steps": steps, "warmup": warmup, "pairs_per_iter": r["N"], "value": r["value"], "unit": "pairs/s",
+         "ms_per_step": r["ms"] / steps, "kernels": r["kernels"], "final_loss_bits": r["final_loss_bits"],
+         "roofline": roofline_of(w, r, steps)}
+    return d
+
+
+def cpu_baseline(w, seconds: float):
+    """The FP64 oracle on the host on whole rows of the workload: each sampled row i is
+    evaluated against all n vertices (its loss and gradient), in batches of 500 seeded
+    random rows until `seconds` have passed.  A row does n - 1 ordered pair evaluations,
+    half of the work the full oracle spends per unordered pair, so the unordered-pair rate
+    is rows (n - 1) / 2 / time; one full iteration is extrapolated from it."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    g = w.graph
+    n = g.n
+    X = w.X0.astype(np.float64)
+    rng = np.random.default_rng(7)
+    rows = 0
+    t0 = time.perf_counter()
+    while True:
+        idx = np.sort(rng.choice(n, size=min(500, n), replace=False)).astype(np.int64)
+        oracle.rows(X, g.row_ptr, g.col_idx, idx, w.mu, w.sigma)
+        rows += idx.size
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    rate = rows * (n - 1) / 2.0 / el
+    N = n * (n - 1) // 2
+    return {"value": rate, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{rows} random rows of {w.name} at X0, each against all {n} vertices (loss and gradient "
+                      f"of the row; FP64 brute force, OpenMP over rows), {el:.1f} s; counted as rows (n-1)/2 "
+                      f"unordered pairs",
+            "extrapolated_s_per_iter": N / rate}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cl3400")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cl1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix pass")
+    ap.add_argument("--no-extras", action="store_true", help="skip the BF16 variant and the other workloads")
+    ap.add_argument("--variant-steps", type=int, default=5, help="timed iterations of the BF16 variant")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 20 times (the reference "
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--record-traffic", default=None, metavar="DIR",
-                    help="only write the k_iter traffic record from the rocprofv3 --pmc runs under DIR "
-                         "(no GPU needed)")
+                    help="only write profiles/traffic_<workload>.json from the rocprofv3 --pmc runs under "
+                         "DIR (no GPU needed); --traffic-kernel names the kernel")
+    ap.add_argument("--traffic-kernel", default="gempe::k_sweep_small<16, 2, 4, 0>")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     args = ap.parse_args()
     if args.record_traffic:
-        record_traffic(args.record_traffic, "gempe::k_iter<2>", "cl3400", 268435456)
+        record_traffic(args.record_traffic, args.traffic_kernel, args.workload, 268435456)
         return
     if args.copy_probe:
         import torch
@@ -216,110 +363,61 @@ def main():
                                    "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2011_03479_amd import gempe, synth
+    from paper_2011_03479_amd import synth
 
-    w = synth.workload(args.workload)
-    steps = args.steps if args.steps is not None else w.iters
-    g = w.graph
-    n, d = g.n, w.d
-    N = n * (n - 1) // 2
     torch.cuda.set_device(0)
-    G = gempe.Graph(n, g.row_ptr, g.col_idx)
-    params = gempe.params_default(precision=gempe.GEMPE_BF16_GRAM if w.precision == "bf16" else gempe.GEMPE_FP32)
-    ws = gempe.workspace(G, d, params)
-    X0 = torch.as_tensor(w.X0, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    # warm-up
-    X = X0.clone()
-    if args.warmup > 0:
-        gempe.embed(G, X, args.warmup, w.eta, ws=ws, params=params)
-    torch.cuda.synchronize()
-
-    # timed region: exactly `steps` iterations from X0
-    X = X0.clone()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    gempe.embed(G, X, steps, w.eta, ws=ws, params=params)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
-    value = N * steps / (ms / 1e3)
-
-    # Dominant kernel.  Small n: the fused iteration kernel (one launch per step, so the
-    # timed region above is `steps` back-to-back launches of it plus two tiny kernels);
-    # large n: the sweep launched inside each step.  Its average duration is bounded by the
-    # per-step time measured with HIP events on the stream the kernels run on.
-    k_ms = ms / steps
-    if w.precision == "bf16":
-        # MFMA-bound screen: 2d BF16 MFMA flops per pair for the Gram term
-        fpp, peak, bound = 2 * d, PEAK_BF16_TFLOPS, "mfma"
-        plan_kernel = "k_gram_screen (BF16 MFMA Gram screen; kernel_ms is the whole step, an upper bound)"
-    else:
-        fpp, peak, bound = flops_per_pair(d), PEAK_FP32_TFLOPS, "alu"
-        plan_kernel = "k_iter (fused iteration: all-pairs sweep, exact edge pass, update)" if n <= 23000 and d <= 16 \
-            else "k_sweep_small / k_sweep_wide (per step, with the edge pass and update)"
-    achieved = fpp * N / (k_ms / 1e3) / 1e12
-
+    t_gen = time.perf_counter()
+    w = synth.workload(args.workload)
+    gen_s = time.perf_counter() - t_gen
+    steps = args.steps if args.steps is not None else w.iters
+    print(f"# {w.name}: n={w.graph.n} m={w.graph.m} d={w.d} generated in {gen_s:.1f} s; "
+          f"{args.warmup} + {steps} iterations", file=sys.stderr, flush=True)
+    r = gd_run(w, steps, args.warmup)
+    main_sum = summary(w, r, steps, args.warmup)
+    roof = main_sum["roofline"]
+    if w.precision == "fp32" and w.d <= 16 and w.graph.n > 23000:
+        attach_traffic(roof, args.traffic_kernel, w.name)
     result = {
-        "metric": "vertex-pairs/s per full-gradient iteration",
-        "value": value,
+        "metric": "vertex-pairs/s per full-gradient iteration (FP32; BF16-MFMA Gram variant under variants)",
+        "value": r["value"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / steps,
+        "ms_per_step": r["ms"] / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if w.precision == "fp32" else "bf16+f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": n, "m": g.m, "d": d, "iters": steps,
-                   "pairs_per_iter": N, "eta": w.eta, "mu": w.mu, "sigma": w.sigma,
-                   "precision": w.precision},
-        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": plan_kernel, "kernel_ms": k_ms, "flops_per_pair": fpp},
-        "wall_s": wall,
-        "final_loss_bits": None,
+        "config": {"workload": w.name, "n": w.graph.n, "m": w.graph.m, "d": w.d, "iters": steps,
+                   "pairs_per_iter": r["N"], "eta": w.eta, "mu": w.mu, "sigma": w.sigma,
+                   "precision": w.precision, "graph": "Chung-Lu power law, mean degree 20, exponent 2.3"
+                   if w.name.startswith("cl1m") else w.name},
+        "roofline": roof,
+        "kernels": r["kernels"],
+        "wall_s": r["wall_s"],
+        "final_loss_bits": r["final_loss_bits"],
     }
-    tr = measured_traffic("gempe::k_iter<2>", w.name) if plan_kernel.startswith("k_iter") and d == 2 else None
-    if tr is not None:
-        result["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
-        result["roofline"]["traffic_detail"] = {
-            "unit": "bytes per launch", "fetch": tr["fetch_bytes_per_launch"], "write": tr["write_bytes_per_launch"],
-            "fetch_factor": tr["fetch_factor"], "write_factor": tr["write_factor"],
-            "source": "profiles/k_iter_cl3400_traffic.json (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)"}
-    hist = torch.empty(1, dtype=torch.float64, device="cuda")
-    gempe.loss_grad(G, X, ws=ws, params=params, out=gempe.LossGrad(hist, None, None, None))
-    torch.cuda.synchronize()
-    result["final_loss_bits"] = float(hist.item())
-
+    print(f"# {w.name}: {r['ms'] / steps:.3f} ms/iteration, {r['value']:.4g} pairs/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        import oracle
-
-        oracle.build(force=False)
-        Xc = w.X0.astype(np.float64)
-        t0 = time.perf_counter()
-        its = 0
-        while True:
-            oracle.loss_grad(Xc, g.row_ptr, g.col_idx, w.mu, w.sigma)
-            its += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        el = time.perf_counter() - t0
-        result["cpu_baseline"] = {
-            "value": N * its / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{its} full loss+gradient evaluations of {w.name} at X0 (FP64 brute force over all "
-                      f"ordered pairs, OpenMP over rows), {el:.1f} s",
-        }
+        result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        print(f"# cpu baseline: {result['cpu_baseline']['value']:.4g} pairs/s", file=sys.stderr, flush=True)
+    if not args.no_extras:
+        if w.name == "cl1m":
+            wb = synth.Workload("cl1m_bf16", w.graph, w.d, w.X0, w.iters, w.eta, "bf16")
+            rb = gd_run(wb, args.variant_steps, 1)
+            result["variants"] = {"cl1m_bf16": summary(wb, rb, args.variant_steps, 1)}
+            print(f"# cl1m_bf16: {rb['ms'] / args.variant_steps:.3f} ms/iteration", file=sys.stderr, flush=True)
+        del w
+        result["extras"] = {}
+        for name, st, wu in (("cl3400", 1000, 20), ("sbm100k", 20, 2)):
+            we = synth.workload(name)
+            re_ = gd_run(we, st, wu)
+            result["extras"][name] = summary(we, re_, st, wu)
+            print(f"# {name}: {re_['ms'] / st:.4f} ms/iteration", file=sys.stderr, flush=True)
     if not args.no_serve:
         result["serving"] = serving_bench(args.serve_jobs, args.serve_load, args.serve_budget_gib, 10, 6000)
     print(json.dumps(result))

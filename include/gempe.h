@@ -17,8 +17,9 @@
  * gradient is 0, the convention Eq. 5 uses for s_ij.
  *
  * Conventions for every call:
- *   - Pointers are DEVICE pointers unless marked [host].  The caller owns all memory
- *     passed in; the library owns what a graph handle allocates in gempe_graph_create.
+ *   - Pointers are DEVICE pointers unless marked [host].  The caller owns all device
+ *     memory, the graph's included (gempe_graph_workspace_bytes); the library allocates
+ *     device memory only for a server's budget block (gempe_server_create).
  *   - Matrices are row-major: X and grad are n x d float32, vertex i at X + i*d.
  *   - Vertex ids are 0-based; col_idx is int32 (n < 2^31), row_ptr is int64.
  *   - No exceptions cross the ABI.  Every call returns a gempe_status; argument errors
@@ -88,22 +89,33 @@ void gempe_params_default(gempe_params *p);
 
 typedef struct gempe_graph_s *gempe_graph;
 
+/* Bytes of device memory a graph handle needs for n vertices and nnz CSR entries (the
+ * CSR copy, the row id of every entry, the exact edge hash and a few status words; a graph
+ * of n = 1e6 vertices and m = 1e7 edges needs about 440 MB).  0 on invalid arguments. [host] */
+size_t gempe_graph_workspace_bytes(int32_t n, int64_t nnz);
+
 /*
  * Uploads and validates a graph (Sec. II-A: n vertices, m undirected, unweighted,
  * unlabeled edges) given as symmetric CSR on the device:
  *   row_ptr : int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx : int32[nnz], nnz = 2m; each row sorted strictly ascending, no self-loops,
  *             every (i, j) present together with (j, i)
- * The library copies the CSR (the caller may free its buffers after return) and builds
- * an exact open-addressing hash of the m undirected edges (64-bit keys, capacity the
- * power of two >= 2m, load factor <= 0.5) in device memory.  Synchronous: returns after
- * validation; GEMPE_ERR_GRAPH if the CSR violates any rule above.  *out [host] receives
- * the handle; n >= 1, nnz >= 0.
+ *   ws      : device memory of ws_bytes >= gempe_graph_workspace_bytes(n, nnz), 256-byte
+ *             aligned, owned by the caller; it holds the graph for the handle's lifetime
+ *             and must stay valid until the last call using the handle has completed
+ * The library copies the CSR into ws (the caller may free its CSR buffers after return)
+ * and builds there an exact open-addressing hash of the m undirected edges (64-bit keys,
+ * capacity the power of two >= 2m, load factor <= 0.5); it allocates no device memory.
+ * Synchronous: returns after validation; GEMPE_ERR_GRAPH if the CSR violates any rule
+ * above, GEMPE_ERR_NOMEM if ws_bytes is too small.  *out [host] receives the handle;
+ * n >= 1, nnz >= 0.
  */
 gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t *row_ptr,
-                                const int32_t *col_idx, hipStream_t stream, gempe_graph *out);
+                                const int32_t *col_idx, void *ws, size_t ws_bytes,
+                                hipStream_t stream, gempe_graph *out);
 
-/* Releases the handle and its device memory (synchronises the device first). */
+/* Releases the host-side handle.  Makes no device call: the graph's memory is the caller's
+ * workspace, which the caller frees once the work using the handle has completed. */
 gempe_status gempe_graph_destroy(gempe_graph g);
 
 int32_t gempe_graph_num_vertices(gempe_graph g); /* n, or -1 for a null handle */
@@ -368,6 +380,28 @@ gempe_status gempe_server_get_stats(gempe_server s, gempe_server_stats *out); /*
 /* Stops the scheduler, lets enqueued device work finish, marks unfinished jobs FAILED and
  * frees the server's memory. [host] */
 gempe_status gempe_server_destroy(gempe_server s);
+
+/* ------------------------------------------------------------------------------------
+ * Kernel timing, for measurement.  While enabled, the library records a pair of HIP events
+ * on the launch's own stream around the launches of each kernel class, so that the time
+ * between them is those kernels' device time.  gempe_timing_read waits for the recorded
+ * events of one class, returns the number of kernel launches they bracket and their summed
+ * duration in milliseconds, and clears that class's record.  Enabling costs two event
+ * records per bracket; disabled (the default), nothing is recorded.
+ * ------------------------------------------------------------------------------------ */
+enum {
+    GEMPE_TK_SWEEP = 0,  /* the all-pairs FP32 sweep (one bracket per launch), or the fused
+                            gradient-descent iteration (one bracket over the iterations of a
+                            gempe_embed call, counted as that many launches)               */
+    GEMPE_TK_GRAM = 1,   /* the BF16 MFMA Gram screen                                        */
+    GEMPE_TK_EXACT = 2,  /* the exact FP32 passes over the BF16 screen's near tiles          */
+    GEMPE_TK_EDGES = 3   /* the exact edge correction over the CSR entries                  */
+};
+
+gempe_status gempe_timing_enable(int32_t on); /* [host] */
+/* kclass: GEMPE_TK_*; *launches and *total_ms [host] receive the totals.  GEMPE_ERR_HIP if
+ * an event failed.  [host] */
+gempe_status gempe_timing_read(int32_t kclass, int64_t *launches, double *total_ms);
 
 /* Static description of a status code. [host] */
 const char *gempe_status_string(gempe_status s);

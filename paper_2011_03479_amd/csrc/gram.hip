@@ -581,15 +581,18 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
     else                                                                                                          \
         hipLaunchKernelGGL((k_gram_screen<DD, 2>), grid, block, 0, s, xb, nrm, smax128, n, ntile, Q, nb64, theta0, \
                            flags)
-    switch (d) {
-        case 16: GEMPE_SCREEN(16); break;
-        case 32: GEMPE_SCREEN(32); break;
-        case 48: GEMPE_SCREEN(48); break;
-        case 64: GEMPE_SCREEN(64); break;
-        case 80: GEMPE_SCREEN(80); break;
-        case 96: GEMPE_SCREEN(96); break;
-        case 112: GEMPE_SCREEN(112); break;
-        default: GEMPE_SCREEN(128); break;
+    {
+        TimedLaunches tl(kTkGram, s);
+        switch (d) {
+            case 16: GEMPE_SCREEN(16); break;
+            case 32: GEMPE_SCREEN(32); break;
+            case 48: GEMPE_SCREEN(48); break;
+            case 64: GEMPE_SCREEN(64); break;
+            case 80: GEMPE_SCREEN(80); break;
+            case 96: GEMPE_SCREEN(96); break;
+            case 112: GEMPE_SCREEN(112); break;
+            default: GEMPE_SCREEN(128); break;
+        }
     }
 #undef GEMPE_SCREEN
     const long long t64 = nb64 * (nb64 + 1) / 2;

@@ -219,25 +219,30 @@ gempe_status gempe_graph_build(int32_t n, int64_t nnz, const int64_t *row_ptr, c
     return GEMPE_OK;
 }
 
+extern "C" size_t gempe_graph_workspace_bytes(int32_t n, int64_t nnz) {
+    if (gempe_graph_check_args(n, nnz, "", "", "graph_workspace_bytes") != GEMPE_OK) return 0;
+    return gempe_graph_mem_bytes(n, nnz);
+}
+
 extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t *row_ptr,
-                                           const int32_t *col_idx, hipStream_t stream,
-                                           gempe_graph *out) {
+                                           const int32_t *col_idx, void *ws, size_t ws_bytes,
+                                           hipStream_t stream, gempe_graph *out) {
     if (!out) return gempe_fail(GEMPE_ERR_ARG, "graph_create: out is NULL");
     *out = nullptr;
     gempe_status st = gempe_graph_check_args(n, nnz, row_ptr, col_idx, "graph_create");
     if (st != GEMPE_OK) return st;
-    void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, gempe_graph_mem_bytes(n, nnz));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return gempe_fail(GEMPE_ERR_NOMEM, std::string("graph_create: hipMalloc: ") + hipGetErrorString(e));
-    }
+    if (!ws) return gempe_fail(GEMPE_ERR_ARG, "graph_create: null workspace");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return gempe_fail(GEMPE_ERR_ARG, "graph_create: workspace must be 256-byte aligned");
+    const size_t need = gempe_graph_mem_bytes(n, nnz);
+    if (ws_bytes < need)
+        return gempe_fail(GEMPE_ERR_NOMEM, "graph_create: workspace of " + std::to_string(ws_bytes) +
+                                               " bytes, need " + std::to_string(need));
     gempe_graph_s *g = new gempe_graph_s();
-    g->owns_mem = true;
-    st = gempe_graph_build(n, nnz, row_ptr, col_idx, hipMemcpyDeviceToDevice, mem, stream, g);
+    st = gempe_graph_build(n, nnz, row_ptr, col_idx, hipMemcpyDeviceToDevice, ws, stream, g);
     if (st != GEMPE_OK) {
+        // nothing may still be running on the caller's memory when the error returns
         (void)hipStreamSynchronize(stream);
-        (void)hipFree(mem);
         delete g;
         return st;
     }
@@ -247,9 +252,8 @@ extern "C" gempe_status gempe_graph_create(int32_t n, int64_t nnz, const int64_t
 
 extern "C" gempe_status gempe_graph_destroy(gempe_graph g) {
     if (!g) return gempe_fail(GEMPE_ERR_ARG, "graph_destroy: null handle");
-    if (!g->owns_mem) return gempe_fail(GEMPE_ERR_ARG, "graph_destroy: handle is owned by a server");
-    GEMPE_HIP_TRY(hipDeviceSynchronize());
-    (void)hipFree(g->mem);
+    if (g->server_owned) return gempe_fail(GEMPE_ERR_ARG, "graph_destroy: handle is owned by a server");
+    // the device memory belongs to the caller; only the host-side handle is released
     delete g;
     return GEMPE_OK;
 }

@@ -31,8 +31,8 @@ struct gempe_graph_s {
     unsigned long long *hash = nullptr;  // device, open addressing, capacity hash_cap
     uint64_t hash_cap = 0;       // power of two >= 2m (>= 2)
     unsigned *status_dev = nullptr;  // device words: [0] graph validation, [1] counters
-    void *mem = nullptr;         // the one device block holding all of the above
-    bool owns_mem = false;       // allocated by gempe_graph_create (else by a server's arena)
+    void *mem = nullptr;         // the one device block holding all of the above (caller's workspace)
+    bool server_owned = false;   // carved from a server's arena (released by the server)
 };
 
 // Host-side size checks shared by gempe_graph_create and the server's submit.
@@ -47,6 +47,26 @@ gempe_status gempe_graph_build(int32_t n, int64_t nnz, const int64_t *row_ptr, c
 
 // Empty slot marker of the edge hash (keys are (min << 32) | max with min < max < 2^31).
 constexpr unsigned long long kHashEmpty = ~0ull;
+
+// Kernel timing brackets (timing.hip); the classes are gempe.h's GEMPE_TK_*.
+enum { kTkSweep = GEMPE_TK_SWEEP, kTkGram = GEMPE_TK_GRAM, kTkExact = GEMPE_TK_EXACT, kTkEdges = GEMPE_TK_EDGES,
+       kTkClasses = 4 };
+bool gempe_timing_on();
+void gempe_timing_begin(int cls, hipStream_t s);
+void gempe_timing_end(int cls, hipStream_t s, int launches);
+// Scoped bracket: events on `s` before and after the launches made while it lives.
+struct TimedLaunches {
+    int cls;
+    hipStream_t s;
+    int launches;
+    bool on;
+    TimedLaunches(int c, hipStream_t st, int nl = 1) : cls(c), s(st), launches(nl), on(gempe_timing_on()) {
+        if (on) gempe_timing_begin(cls, s);
+    }
+    ~TimedLaunches() {
+        if (on) gempe_timing_end(cls, s, launches);
+    }
+};
 
 // Host-side checks of (n, d, params) shared by every call (api.hip).
 gempe_status gempe_check_problem(int32_t n, int32_t d, const gempe_params *p, const char *who);

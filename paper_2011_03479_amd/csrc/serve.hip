@@ -221,6 +221,7 @@ bool gempe_server_s::admit_one(Job *j) {
     j->base = block + off;
     gempe_status st = gempe_graph_build(j->n, j->nnz, j->row_ptr.data(), j->col_idx.data(), hipMemcpyHostToDevice,
                                         j->base + j->J.graph, xfer_stream, &j->graph);
+    j->graph.server_owned = true;
     if (st != GEMPE_OK) {
         (void)hipStreamSynchronize(xfer_stream);
         fail_job(j, st, gempe_last_error());

@@ -705,10 +705,12 @@ struct IterArgs {
     PairParams P;
 };
 
+// The FP64 loss of iteration k's sweep: stored when a history is kept, and checked for
+// being finite in every case (the status word then reports a diverged run).
 __device__ inline void reduce_loss(const IterArgs &a, int k, double *sh) {
     double tot = block_sum_fixed(a.P0 + (size_t)(k & 1) * a.units, a.units, sh);
     if (threadIdx.x == 0) {
-        a.loss_hist[k] = tot;
+        if (a.loss_hist) a.loss_hist[k] = tot;
         if (!isfinite(tot)) atomicOr(a.status, kStatusNonFinite);
     }
 }
@@ -750,7 +752,7 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     if (b >= a.units) {  // uniform over the workgroup
         // the last workgroup sums iteration k-1's loss partials, beside the tiles rather
         // than before one of them
-        if (b == a.units && k > 0 && a.loss_hist) reduce_loss(a, k - 1, sh);
+        if (b == a.units && k > 0) reduce_loss(a, k - 1, sh);
         return;
     }
     stage_ltab2(L.tab, a.P.slope_k);
@@ -858,7 +860,7 @@ __global__ __launch_bounds__(256) void k_iter(IterArgs a, int k) {
 __device__ __forceinline__ void finish_body(const IterArgs &a, int K, int iters, int b, long long gtid,
                                             long long nthreads, double *sh) {
     const long long nd = (long long)a.n * a.d;
-    if (b == 0 && K > 0 && a.loss_hist) reduce_loss(a, K - 1, sh);
+    if (b == 0 && K > 0) reduce_loss(a, K - 1, sh);
     if (iters <= 0) return;
     if (K == iters + 1) {  // x_iters was written to slot iters&1 by the last sweep
         if (iters & 1)
@@ -1183,7 +1185,10 @@ void launch_sweep(const SweepPlan &pl, hipStream_t s, const float *X, int n, int
 template <int D>
 void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_t s) {
     const unsigned grid = (unsigned)pl.iter_blocks;
-    for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_iter<D>, dim3(grid), dim3(256), 0, s, a, k);
+    {
+        TimedLaunches tl(kTkSweep, s, K);
+        for (int k = 0; k < K; ++k) hipLaunchKernelGGL(k_iter<D>, dim3(grid), dim3(256), 0, s, a, k);
+    }
     const long long nd = (long long)a.n * a.d;
     const unsigned fgrid = (unsigned)std::min<long long>(1024, std::max<long long>(1, (nd + 255) / 256));
     hipLaunchKernelGGL(k_iter_finish, dim3(fgrid), dim3(256), 0, s, a, K, iters);
@@ -1201,10 +1206,14 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     const int n = g->n;
     if (plan.bf16) {
         // near pairs of sparsely flagged tiles exactly, the dense tiles by the LDS tile pass
+        TimedLaunches tl(kTkExact, s, 2);
         (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s);
         launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
-    } else
+    } else {
+        TimedLaunches tl(kTkSweep, s);
         launch_sweep<EX>(plan, s, X, n, d, grad, extra, partials, P);
+    }
+    TimedLaunches tl(kTkEdges, s);
     float *epart = partials + plan.items;
     if (plan.D > 16) {
         // wide: one wave per CSR row (also writes the partial of rows without edges)

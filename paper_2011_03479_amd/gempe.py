@@ -7,8 +7,10 @@ fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -34,6 +36,7 @@ GEMPE_F_REVERSE_TILES = 1  # FP32 sweeps take their tiles in reverse order
 # Every symbol include/gempe.h declares (checked by the tests).
 ABI_SYMBOLS = (
     "gempe_params_default",
+    "gempe_graph_workspace_bytes",
     "gempe_graph_create",
     "gempe_graph_destroy",
     "gempe_graph_num_vertices",
@@ -45,6 +48,8 @@ ABI_SYMBOLS = (
     "gempe_shard_rows",
     "gempe_step",
     "gempe_embed",
+    "gempe_timing_enable",
+    "gempe_timing_read",
     "gempe_status_string",
     "gempe_last_error",
     "gempe_wm_terms",
@@ -149,7 +154,10 @@ def load(path: str | None = None):
     P = ctypes.POINTER(gempe_params)
     lib.gempe_params_default.argtypes = [P]
     lib.gempe_params_default.restype = None
-    lib.gempe_graph_create.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.gempe_graph_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.gempe_graph_workspace_bytes.restype = ctypes.c_size_t
+    lib.gempe_graph_create.argtypes = [ctypes.c_int32, ctypes.c_int64, vp, vp, vp, ctypes.c_size_t, vp,
+                                       ctypes.POINTER(vp)]
     lib.gempe_graph_create.restype = st
     lib.gempe_graph_destroy.argtypes = [vp]
     lib.gempe_graph_destroy.restype = st
@@ -173,6 +181,10 @@ def load(path: str | None = None):
     lib.gempe_embed.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_float, vp, vp,
                                 ctypes.c_size_t, P, vp]
     lib.gempe_embed.restype = st
+    lib.gempe_timing_enable.argtypes = [ctypes.c_int32]
+    lib.gempe_timing_enable.restype = st
+    lib.gempe_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    lib.gempe_timing_read.restype = st
     lib.gempe_status_string.argtypes = [st]
     lib.gempe_status_string.restype = ctypes.c_char_p
     lib.gempe_last_error.argtypes = []
@@ -237,6 +249,25 @@ def params_default(**over) -> gempe_params:
     return p
 
 
+GEMPE_TK_SWEEP = 0
+GEMPE_TK_GRAM = 1
+GEMPE_TK_EXACT = 2
+GEMPE_TK_EDGES = 3
+
+
+def timing_enable(on: bool = True):
+    """Brackets the library's kernel launches with HIP events (gempe_timing_enable)."""
+    _check(load().gempe_timing_enable(1 if on else 0))
+
+
+def timing_read(kclass: int) -> tuple[int, float]:
+    """(launches, total milliseconds) recorded for one kernel class since the last read."""
+    nl = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().gempe_timing_read(int(kclass), ctypes.byref(nl), ctypes.byref(ms)))
+    return int(nl.value), float(ms.value)
+
+
 def status_string(s: int) -> str:
     return load().gempe_status_string(int(s)).decode()
 
@@ -265,12 +296,29 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+# Live handles, closed at interpreter exit before the HIP runtime shuts down (a handle
+# released during module teardown could otherwise reach the runtime after its own
+# finalisation has begun).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_handles():
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class Graph:
-    """Owns a gempe_graph handle built from CSR arrays (numpy or CUDA tensors)."""
+    """Owns a gempe_graph handle built from CSR arrays (numpy or CUDA tensors), and the
+    device workspace (a torch uint8 tensor) that holds the graph."""
 
     def __init__(self, n: int, row_ptr, col_idx, device="cuda", stream=None):
         torch = _torch()
         lib = load()
+        self.handle = None
         rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64) if not torch.is_tensor(row_ptr) else row_ptr,
                              dtype=torch.int64, device=device).contiguous()
         ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32) if not torch.is_tensor(col_idx) else col_idx,
@@ -280,11 +328,15 @@ class Graph:
             nnz = 0
         else:
             nnz = int(ci.numel())
+        nbytes = int(lib.gempe_graph_workspace_bytes(int(n), nnz))
+        self.mem = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
-        _check(lib.gempe_graph_create(int(n), nnz, _ptr(rp), _ptr(ci), _stream(stream), ctypes.byref(h)))
+        _check(lib.gempe_graph_create(int(n), nnz, _ptr(rp), _ptr(ci), _ptr(self.mem), nbytes, _stream(stream),
+                                      ctypes.byref(h)))
         self.handle = h
         self.n = int(n)
         self.nnz = nnz
+        _live.add(self)
 
     @property
     def m(self) -> int:
@@ -294,9 +346,18 @@ class Graph:
         return int(load().gempe_graph_num_vertices(self.handle))
 
     def close(self):
+        """Releases the handle (no device call) and drops the reference to its memory;
+        torch reuses that memory only after the work queued on its stream."""
         if getattr(self, "handle", None) is not None and self.handle.value:
             _check(load().gempe_graph_destroy(self.handle))
             self.handle = None
+        self.mem = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:
@@ -577,10 +638,12 @@ class Server:
     the library into numpy arrays this object keeps per job until `result` is called."""
 
     def __init__(self, budget_bytes: int, max_jobs: int = 256):
+        self.handle = None
         h = ctypes.c_void_p()
         _check(load().gempe_server_create(int(budget_bytes), int(max_jobs), ctypes.byref(h)))
         self.handle = h
         self._out = {}
+        _live.add(self)
 
     def submit(self, n, row_ptr, col_idx, X0, iters: int, eta: float, params=None, release_s: float = 0.0,
                want_hist: bool = True) -> int:

@@ -49,11 +49,26 @@ def test_params_default_and_status_strings(lib):
 
 def test_host_side_argument_checks(lib):
     out = ctypes.c_void_p()
-    assert lib.gempe_graph_create(10, 0, None, None, None, None) == gempe.GEMPE_ERR_ARG
-    assert lib.gempe_graph_create(0, 0, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_ARG
-    assert lib.gempe_graph_create(10, 3, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
-    assert lib.gempe_graph_create(3, 8, None, None, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
+    assert lib.gempe_graph_create(10, 0, None, None, None, 0, None, None) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_graph_create(0, 0, None, None, None, 0, None, ctypes.byref(out)) == gempe.GEMPE_ERR_ARG
+    assert lib.gempe_graph_create(10, 3, None, None, None, 0, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
+    assert lib.gempe_graph_create(3, 8, None, None, None, 0, None, ctypes.byref(out)) == gempe.GEMPE_ERR_GRAPH
     assert "nnz" in gempe.last_error()
+    # the graph's device memory is the caller's: size query, then the workspace checks run
+    # on the host before anything touches the (here fake, never dereferenced) pointers
+    need = lib.gempe_graph_workspace_bytes(1000, 20000)
+    assert need >= 8 * 1001 + 2 * 4 * 20000 + 8 * 2 * 10000
+    assert lib.gempe_graph_workspace_bytes(0, 0) == 0 and lib.gempe_graph_workspace_bytes(10, 3) == 0
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.gempe_graph_create(1000, 20000, fake, fake, None, need, None, ctypes.byref(out)) == \
+        gempe.GEMPE_ERR_ARG
+    assert "workspace" in gempe.last_error()
+    assert lib.gempe_graph_create(1000, 20000, fake, fake, ctypes.c_void_p(0x1010), need, None,
+                                  ctypes.byref(out)) == gempe.GEMPE_ERR_ARG
+    assert "aligned" in gempe.last_error()
+    assert lib.gempe_graph_create(1000, 20000, fake, fake, fake, need - 1, None, ctypes.byref(out)) == \
+        gempe.GEMPE_ERR_NOMEM
+    assert out.value is None
     p = gempe.params_default()
     assert lib.gempe_workspace_bytes(None, 2, ctypes.byref(p)) == 0
     assert lib.gempe_loss_grad(None, 2, None, None, None, None, None, None, 0, ctypes.byref(p), None) == \

@@ -277,6 +277,21 @@ def test_workspace_and_argument_errors():
     with pytest.raises(gempe.GempeError) as e:
         gempe.embed(G, bad, iters=2, eta=1e-3, ws=ws, loss_hist=hist)
     assert e.value.status == gempe.GEMPE_ERR_NUMERIC
+    # without a loss history the fused iteration (n <= 23,000, d <= 16) still reduces and
+    # checks every sweep's loss, and the per-evaluation path (d = 32) its scratch loss
+    note("NaN without a loss history: fused (d = 2) and per-evaluation (d = 32) paths")
+    for d in (2, 32):
+        Gd = gempe.Graph(100, g.row_ptr, g.col_idx)
+        wsd = gempe.workspace(Gd, d)
+        Xd = to_dev(synth.init_embedding(100, d, 4))
+        Xd[7, d - 1] = float("nan")
+        for iters in (1, 3):
+            with pytest.raises(gempe.GempeError) as e:
+                gempe.embed(Gd, Xd.clone(), iters=iters, eta=1e-3, ws=wsd)
+            assert e.value.status == gempe.GEMPE_ERR_NUMERIC, (d, iters)
+        # and a finite run on the same workspace reports no error afterwards
+        gempe.embed(Gd, to_dev(synth.init_embedding(100, d, 4)), iters=3, eta=1e-3, ws=wsd)
+        Gd.close()
 
 
 def test_er1k_trajectory():
