@@ -197,6 +197,32 @@ gempe_status gempe_embed(gempe_graph g, int32_t d, float *X, int32_t iters, floa
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): gempe_loss_grad with the library's own
+ * device scratch in place of the caller's workspace.
+ * ------------------------------------------------------------------------------------ */
+#define GEMPE_NOALLOC_SCRATCH_BYTES (32u << 20) /* per device, held until the process ends */
+
+/* Scratch bytes gempe_loss_grad_noalloc needs for this problem: one float loss partial per
+ * sweep tile and per edge block, plus 8.5 KiB of counters and reduction slots (n = 1e6 at
+ * d = 16 needs about 8 MB; above about n = 190,000 at d > 16 it exceeds the array).  0 on
+ * invalid arguments or BF16_GRAM. [host] */
+size_t gempe_loss_grad_noalloc_bytes(gempe_graph g, int32_t d, const gempe_params *p);
+
+/* gempe_loss_grad without a workspace argument: the same arguments otherwise (X, grad and
+ * loss required), the same kernels and results, FP32 only.  Allocates nothing and calls no
+ * allocating routine (unless gempe_timing_enable is on, whose brackets create HIP events):
+ * its scratch is a file-scope device array of GEMPE_NOALLOC_SCRATCH_BYTES, one per device,
+ * that every call on that device shares and that keeps the last call's contents (each call
+ * clears what must start at zero).  Calls that overlap on one device race on the array:
+ * the caller serialises them (one stream, or events).  GEMPE_ERR_NOMEM when
+ * gempe_loss_grad_noalloc_bytes exceeds GEMPE_NOALLOC_SCRATCH_BYTES; GEMPE_ERR_UNSUPPORTED
+ * for BF16_GRAM.  Asynchronous. */
+gempe_status gempe_loss_grad_noalloc(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
+                                     int64_t *edge_hits, float *row_loss, const gempe_params *p,
+                                     hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Weighted majorization (Sec. II-C).  For each pair the parabola w_ij (delta - d_ij)^2 that
  * matches dl's slope and curvature at the current distance (Eqs. 3-4) has
  *   w_ij = dl''(delta_ij) / 2 = R (R + tau) / (2 sigma^2 ln 2),  R = phi(tau) / Phi(tau)

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -472,5 +473,77 @@ extern "C" gempe_status gempe_embed_sampled(gempe_graph g, int32_t d, float *X, 
                                  stream));
     GEMPE_HIP_TRY(hipStreamSynchronize(stream));
     if (host_status & kStatusNonFinite) return gempe_fail(GEMPE_ERR_NUMERIC, "embed_sampled: non-finite loss");
+    return GEMPE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Loss and gradient without any allocation: the scratch of the evaluation (counters, loss
+// partials, the first FP64 reduction level) lives in a file-scope device array instead of
+// a caller workspace.  Every device the library runs on holds its own copy of the array
+// until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a host-side
+// stand-in, not a device address).
+// ------------------------------------------------------------------------------------
+
+namespace {
+constexpr size_t kScratchBytes = size_t(GEMPE_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array, looked up once per device.
+gempe_status scratch_for_current_device(unsigned char **out) {
+    int dev = 0;
+    GEMPE_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_noalloc: device id out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return gempe_fail(GEMPE_ERR_HIP, std::string("loss_grad_noalloc: hipGetSymbolAddress: ") +
+                                                 hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    return GEMPE_OK;
+}
+}  // namespace
+
+extern "C" size_t gempe_loss_grad_noalloc_bytes(gempe_graph g, int32_t d, const gempe_params *p) {
+    if (check_common(g, d, p, "loss_grad_noalloc_bytes") != GEMPE_OK) return 0;
+    if (p->precision != GEMPE_FP32) {
+        gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_noalloc_bytes: FP32 only");
+        return 0;
+    }
+    return gempe_ws_layout_eval(g, d, gempe_make_plan(g, d, false)).total;
+}
+
+extern "C" gempe_status gempe_loss_grad_noalloc(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
+                                                int64_t *edge_hits, float *row_loss, const gempe_params *p,
+                                                hipStream_t stream) {
+    gempe_status st = check_common(g, d, p, "loss_grad_noalloc");
+    if (st != GEMPE_OK) return st;
+    if (p->precision != GEMPE_FP32)
+        return gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_noalloc: FP32 only (the BF16 screen needs a workspace)");
+    if (!X || !grad || !loss) return gempe_fail(GEMPE_ERR_ARG, "loss_grad_noalloc: X, grad and loss are required");
+    const SweepPlan plan = gempe_make_plan(g, d, false);
+    const WsLayout L = gempe_ws_layout_eval(g, d, plan);
+    if (L.total > kScratchBytes)
+        return gempe_fail(GEMPE_ERR_NOMEM, "loss_grad_noalloc: the evaluation needs " + std::to_string(L.total) +
+                                               " bytes of scratch, the static array holds " +
+                                               std::to_string(kScratchBytes));
+    unsigned char *w = nullptr;
+    if ((st = scratch_for_current_device(&w)) != GEMPE_OK) return st;
+    // the counters are cleared by the evaluation's first kernel, every partial slot is
+    // written by its tile or edge block, the reduction level by k_reduce1
+    GEMPE_HIP_TRY(gempe_launch_loss_grad(g, d, plan, X, grad, row_loss, reinterpret_cast<float *>(w + L.partials),
+                                         w + L.counters, loss, edge_hits, gempe_pair_params(p), stream, true,
+                                         GramCtx(), reinterpret_cast<double *>(w + L.red)));
     return GEMPE_OK;
 }

@@ -165,6 +165,9 @@ struct WsLayout {
 
 SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16);
 WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
+// The part of the layout one FP32 loss/gradient evaluation with a caller-provided gradient
+// uses: counters, loss partials and the first reduction level only.
+WsLayout gempe_ws_layout_eval(const gempe_graph_s *g, int d, const SweepPlan &plan);
 
 // Kernel launchers (sweep.hip).
 struct PairParamsHost {

@@ -1067,6 +1067,21 @@ WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     return L;
 }
 
+WsLayout gempe_ws_layout_eval(const gempe_graph_s *g, int d, const SweepPlan &plan) {
+    (void)g;
+    (void)d;
+    WsLayout L;
+    size_t off = 0;
+    L.counters = off;
+    off += 256;
+    L.partials = off;
+    off = align256(off + sizeof(float) * (size_t)plan.partials);
+    L.red = off;
+    off = align256(off + sizeof(double) * kRed1Blocks);
+    L.total = off;
+    return L;
+}
+
 GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p) {
     GramCtx c;
     if (!L.xb) return c;

@@ -44,6 +44,8 @@ ABI_SYMBOLS = (
     "gempe_has_edge",
     "gempe_workspace_bytes",
     "gempe_loss_grad",
+    "gempe_loss_grad_noalloc_bytes",
+    "gempe_loss_grad_noalloc",
     "gempe_loss_grad_shard",
     "gempe_shard_rows",
     "gempe_step",
@@ -171,6 +173,10 @@ def load(path: str | None = None):
     lib.gempe_workspace_bytes.restype = ctypes.c_size_t
     lib.gempe_loss_grad.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, P, vp]
     lib.gempe_loss_grad.restype = st
+    lib.gempe_loss_grad_noalloc_bytes.argtypes = [vp, ctypes.c_int32, P]
+    lib.gempe_loss_grad_noalloc_bytes.restype = ctypes.c_size_t
+    lib.gempe_loss_grad_noalloc.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, P, vp]
+    lib.gempe_loss_grad_noalloc.restype = st
     lib.gempe_loss_grad_shard.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, vp,
                                           ctypes.c_size_t, P, vp]
     lib.gempe_loss_grad_shard.restype = st
@@ -417,6 +423,34 @@ def loss_grad(g: Graph, X, ws=None, params=None, want_grad=True, want_hits=True,
         )
     _check(load().gempe_loss_grad(g.handle, int(d), _ptr(X), _ptr(out.grad), _ptr(out.loss), _ptr(out.edge_hits),
                                   _ptr(out.row_loss), _ptr(ws), int(ws.numel()), ctypes.byref(p), _stream(stream)))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20  # GEMPE_NOALLOC_SCRATCH_BYTES
+
+
+def loss_grad_noalloc_bytes(g: Graph, d: int, params=None) -> int:
+    p = params or params_default()
+    return int(load().gempe_loss_grad_noalloc_bytes(g.handle, int(d), ctypes.byref(p)))
+
+
+def loss_grad_noalloc(g: Graph, X, params=None, want_hits=True, want_row_loss=False, stream=None,
+                      out: LossGrad | None = None) -> LossGrad:
+    """gempe_loss_grad_noalloc: the loss and gradient with the library's static scratch
+    (no workspace); outputs are allocated here unless `out` is given."""
+    torch = _torch()
+    n, d = X.shape
+    p = params or params_default()
+    if out is None:
+        out = LossGrad(
+            loss=torch.empty(1, dtype=torch.float64, device="cuda"),
+            grad=torch.empty((n, d), dtype=torch.float32, device="cuda"),
+            edge_hits=torch.empty(1, dtype=torch.int64, device="cuda") if want_hits else None,
+            row_loss=torch.empty(n, dtype=torch.float32, device="cuda") if want_row_loss else None,
+        )
+    _check(load().gempe_loss_grad_noalloc(g.handle, int(d), _ptr(X), _ptr(out.grad), _ptr(out.loss),
+                                          _ptr(out.edge_hits), _ptr(out.row_loss), ctypes.byref(p),
+                                          _stream(stream)))
     return out
 
 
