@@ -76,7 +76,9 @@ namespace {
 
 gempe_status check_common(gempe_graph g, int32_t d, const gempe_params *p, const char *who) {
     if (!g) return gempe_fail(GEMPE_ERR_ARG, std::string(who) + ": null graph handle");
-    return gempe_check_problem(g->n, d, p, who);
+    gempe_status st = gempe_check_problem(g->n, d, p, who);
+    if (st != GEMPE_OK) return st;
+    return gempe_check_plan(gempe_make_plan(g, d, p->precision == GEMPE_BF16_GRAM), who);
 }
 
 gempe_status check_ws(gempe_graph g, int32_t d, const void *ws, size_t ws_bytes, const WsLayout &L,

@@ -11,8 +11,10 @@
 // Kernels:
 //   k_hist_small<D>  d <= 16: four waves per workgroup, each wave takes whole 64 x 64 tiles
 //                    (rows in registers, columns rotating through the DPP schedule), counts
-//                    in an LDS histogram (one LDS atomic per pair); the workgroup writes its
-//                    histogram to its own slot of a partial buffer (no global atomics).
+//                    in a 32-bit LDS histogram (one LDS atomic per pair); the workgroup adds
+//                    its histogram into its own 64-bit slot of a partial buffer (no global
+//                    atomics) after at most 2^31 pairs and at the end, so no LDS bin can wrap
+//                    whatever n is.
 //   k_hist_wide<D>   d > 16: the workgroup stages a tile's rows and columns in LDS, its four
 //                    waves take 16 steps each, coordinates summed in order.
 //   k_hist_edges     one lane per CSR entry with i < j (the same squared distance), one
@@ -35,6 +37,24 @@ namespace {
 
 constexpr int kHistThreads = 256;
 constexpr int kHistMaxGrid = 512;
+// Rounds of four 64 x 64 tiles a workgroup counts in its 32-bit LDS bins before it adds them
+// into its 64-bit partial histogram: at most 4 * 4096 pairs per round, so no bin can reach
+// 2^32 between flushes.
+constexpr long long kHistFlushRounds = 1ll << 17;
+static_assert(kHistFlushRounds * 4 * 64 * 64 < (1ll << 32), "an LDS bin could wrap between flushes");
+
+// Adds the workgroup's LDS bins into its 64-bit slot (written on the first flush) and clears
+// them.  Called by every thread of the workgroup.
+__device__ __forceinline__ void flush_bins(unsigned *hb, unsigned long long *mine, int nbins, bool &first) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < nbins; q += kHistThreads) {
+        const unsigned long long v = hb[q];
+        mine[q] = first ? v : mine[q] + v;
+        hb[q] = 0u;
+    }
+    first = false;
+    __syncthreads();
+}
 
 __device__ __forceinline__ int bin_of(float r2, float inv_w, float top) {
     return (int)fminf(r2 * inv_w, top);
@@ -43,7 +63,7 @@ __device__ __forceinline__ int bin_of(float r2, float inv_w, float top) {
 template <int D>
 __global__ __launch_bounds__(kHistThreads) void k_hist_small(const float *__restrict__ X, int n, int d, int nt,
                                                              long long tiles, int nbins, float inv_w,
-                                                             unsigned *__restrict__ partial) {
+                                                             unsigned long long *__restrict__ partial) {
     extern __shared__ unsigned hb[];
     for (int q = threadIdx.x; q < nbins; q += kHistThreads) hb[q] = 0u;
     __syncthreads();
@@ -51,7 +71,18 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_small(const float *__rest
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int dir = rot_dir(lane);
     const float top = (float)(nbins - 1);
-    for (long long t = (long long)blockIdx.x * 4 + wave; t < tiles; t += (long long)gridDim.x * 4) {
+    unsigned long long *mine = partial + (size_t)blockIdx.x * nbins;
+    bool first = true;
+    long long rounds = 0;
+    // every wave runs the same number of rounds (a wave past the last tile idles), so the
+    // flushes below are reached by the whole workgroup
+    for (long long t0 = (long long)blockIdx.x * 4; t0 < tiles; t0 += (long long)gridDim.x * 4) {
+        if (++rounds > kHistFlushRounds) {
+            flush_bins(hb, mine, nbins, first);
+            rounds = 1;
+        }
+        const long long t = t0 + wave;
+        if (t >= tiles) continue;
         int I, J;
         tile_of(t, nt, I, J);
         const int i = I * 64 + lane;
@@ -71,14 +102,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_small(const float *__rest
             for (int k = 0; k < D; ++k) xc[k] = rot1(xc[k]);
         }
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nbins; q += kHistThreads) partial[(size_t)blockIdx.x * nbins + q] = hb[q];
+    flush_bins(hb, mine, nbins, first);
 }
 
 template <int D>
 __global__ __launch_bounds__(kHistThreads) void k_hist_wide(const float *__restrict__ X, int n, int d, int nt,
                                                             long long tiles, int nbins, float inv_w,
-                                                            unsigned *__restrict__ partial) {
+                                                            unsigned long long *__restrict__ partial) {
     extern __shared__ unsigned hb[];
     constexpr int S = D + 1;  // padded stride: lane-private rows hit distinct banks
     float *xr = reinterpret_cast<float *>(hb + nbins);  // rows [64][S]
@@ -87,8 +117,16 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_wide(const float *__restr
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const float top = (float)(nbins - 1);
+    unsigned long long *mine = partial + (size_t)blockIdx.x * nbins;
+    bool first = true;
+    long long count = 0;
     // the workgroup stages one 64 x 64 tile; its four waves take 16 of the 64 steps each
     for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
+        if (++count > 4 * kHistFlushRounds) {
+            __syncthreads();  // the previous tile's counts are all in
+            flush_bins(hb, mine, nbins, first);
+            count = 1;
+        }
         int I, J;
         tile_of(t, nt, I, J);
         __syncthreads();  // the previous tile is consumed
@@ -113,8 +151,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_wide(const float *__restr
             if (i < j && j < n) atomicAdd(&hb[bin_of(r2, inv_w, top)], 1u);
         }
     }
-    __syncthreads();
-    for (int q = threadIdx.x; q < nbins; q += kHistThreads) partial[(size_t)blockIdx.x * nbins + q] = hb[q];
+    flush_bins(hb, mine, nbins, first);
 }
 
 __global__ void k_hist_edges(const float *__restrict__ X, int d, const int32_t *__restrict__ coo_row,
@@ -134,7 +171,7 @@ __global__ void k_hist_edges(const float *__restrict__ X, int d, const int32_t *
     atomicAdd(&hist_edge[bin_of(r2, inv_w, (float)(nbins - 1))], 1ull);
 }
 
-__global__ void k_hist_reduce(const unsigned *__restrict__ partial, int parts, int nbins,
+__global__ void k_hist_reduce(const unsigned long long *__restrict__ partial, int parts, int nbins,
                               unsigned long long *__restrict__ hist_all) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbins) return;
@@ -207,13 +244,15 @@ HistPlan hist_plan(int n, int d, int nbins) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <int D>
-void launch_hist_small(const HistPlan &h, const float *X, int n, int d, int nbins, float inv_w, unsigned *partial,
+void launch_hist_small(const HistPlan &h, const float *X, int n, int d, int nbins, float inv_w,
+                       unsigned long long *partial,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_hist_small<D>, dim3(h.grid), dim3(kHistThreads), h.lds, s, X, n, d, h.nt, h.tiles, nbins,
                        inv_w, partial);
 }
 template <int D>
-void launch_hist_wide(const HistPlan &h, const float *X, int n, int d, int nbins, float inv_w, unsigned *partial,
+void launch_hist_wide(const HistPlan &h, const float *X, int n, int d, int nbins, float inv_w,
+                      unsigned long long *partial,
                       hipStream_t s) {
     static bool attr = false;
     if (!attr) {
@@ -262,7 +301,7 @@ using namespace gempe;
 
 size_t gempe_hist_partial_bytes(int n, int d, int nbins) {
     const HistPlan h = hist_plan(n, d, nbins);
-    return align256(sizeof(unsigned) * (size_t)h.grid * (size_t)nbins) + 256;
+    return align256(sizeof(unsigned long long) * (size_t)h.grid * (size_t)nbins) + 256;
 }
 
 hipError_t gempe_launch_histogram(const gempe_graph_s *g, int d, const float *X, int nbins, float r2_max,
@@ -270,7 +309,7 @@ hipError_t gempe_launch_histogram(const gempe_graph_s *g, int d, const float *X,
                                   hipStream_t s) {
     const HistPlan h = hist_plan(g->n, d, nbins);
     const float inv_w = (float)((double)nbins / (double)r2_max);
-    unsigned *partial = static_cast<unsigned *>(scratch);
+    unsigned long long *partial = static_cast<unsigned long long *>(scratch);
     switch (h.D) {
         case 1: launch_hist_small<1>(h, X, g->n, d, nbins, inv_w, partial, s); break;
         case 2: launch_hist_small<2>(h, X, g->n, d, nbins, inv_w, partial, s); break;

@@ -164,6 +164,8 @@ struct WsLayout {
 };
 
 SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16);
+// GEMPE_ERR_UNSUPPORTED when a launch of the plan would exceed HIP's grid limits.
+gempe_status gempe_check_plan(const SweepPlan &p, const char *who);
 WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan);
 // The part of the layout one FP32 loss/gradient evaluation with a caller-provided gradient
 // uses: counters, loss partials and the first reduction level only.

@@ -540,6 +540,7 @@ extern "C" size_t gempe_job_footprint(int32_t n, int64_t nnz, int32_t d, int32_t
     SweepPlan plan;
     WsLayout L;
     job_plan(n, nnz, d, *p, plan, L);
+    if (gempe_check_plan(plan, "job_footprint") != GEMPE_OK) return 0;
     return job_layout(n, nnz, d, iters, L).total;
 }
 
@@ -618,6 +619,7 @@ extern "C" gempe_status gempe_server_submit(gempe_server s, const gempe_job_desc
     j->X_out = jd->X_out;
     j->hist_out = jd->loss_hist;
     job_plan(j->n, j->nnz, j->d, j->params, j->plan, j->L);
+    if ((st = gempe_check_plan(j->plan, "server_submit")) != GEMPE_OK) return st;
     j->J = job_layout(j->n, j->nnz, j->d, j->iters, j->L);
     j->footprint = j->J.total;
     j->batched = j->plan.persist && j->params.precision == GEMPE_FP32 && dclass_of(j->plan.D) >= 0;

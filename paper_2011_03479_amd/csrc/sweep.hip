@@ -1025,6 +1025,20 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
     return p;
 }
 
+gempe_status gempe_check_plan(const SweepPlan &p, const char *who) {
+    if (p.bf16) return GEMPE_OK;  // its launches are bounded by the n limit of BF16_GRAM
+    // the FP32 sweeps launch one workgroup of 64 W threads per tile; HIP bounds a launch to
+    // fewer than 2^32 work-items
+    const long long threads = p.grid * 64LL * p.W;
+    if (p.grid >= (1LL << 31) || threads >= (1LL << 32))
+        return gempe_fail(GEMPE_ERR_UNSUPPORTED,
+                          std::string(who) + ": n too large for one FP32 sweep launch at this d (" +
+                              std::to_string(p.items) + " tiles of " + std::to_string(p.T) +
+                              " rows; the limit is about n = 741,000 for d > 16, 2,960,000 for 5 <= d <= 16 and "
+                              "5,930,000 for d <= 4)");
+    return GEMPE_OK;
+}
+
 WsLayout gempe_ws_layout(const gempe_graph_s *g, int d, const SweepPlan &plan) {
     WsLayout L;
     size_t nd = (size_t)g->n * (size_t)d;

@@ -103,3 +103,15 @@ def test_server_structs_and_host_checks(lib):
     assert lib.gempe_server_create(1 << 20, 4, None) == gempe.GEMPE_ERR_ARG
     assert lib.gempe_server_submit(None, None, None) == gempe.GEMPE_ERR_ARG
     assert lib.gempe_server_destroy(None) == gempe.GEMPE_ERR_ARG
+
+
+def test_sweep_launch_bound_is_checked_on_the_host(lib):
+    """The FP32 sweeps launch a workgroup per tile; a problem whose launch would exceed
+    HIP's 2^32 work-items is refused on the host (GEMPE_ERR_UNSUPPORTED through every
+    entry point; the job footprint query answers 0) instead of failing at launch."""
+    p = gempe.params_default()
+    for n, d in ((741_000, 32), (2_900_000, 16), (5_900_000, 2), (100_000, 128)):
+        assert lib.gempe_job_footprint(n, 2 * n, d, 1, ctypes.byref(p)) > 0, (n, d)
+    for n, d in ((742_000, 32), (1_000_000, 128), (3_000_000, 16), (6_000_000, 3), (2_000_000_000, 2)):
+        assert lib.gempe_job_footprint(n, 2 * n, d, 1, ctypes.byref(p)) == 0, (n, d)
+        assert "too large" in gempe.last_error()
