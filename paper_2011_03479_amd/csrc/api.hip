@@ -515,6 +515,17 @@ gempe_status scratch_for_current_device(unsigned char **out) {
     *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
     return GEMPE_OK;
 }
+
+// The evaluation plan of the static-scratch entry point: the matrix-core sweep's one partial
+// per item when that fits the array, else the vector sweep's fewer, larger tiles.
+SweepPlan noalloc_plan(gempe_graph g, int32_t d) {
+    SweepPlan plan = gempe_make_plan(g, d, false);
+    if (plan.mfma && gempe_ws_layout_eval(g, d, plan).total > kScratchBytes) {
+        plan.mfma = false;
+        plan.partials = plan.items + plan.edge_blocks;
+    }
+    return plan;
+}
 }  // namespace
 
 extern "C" size_t gempe_loss_grad_noalloc_bytes(gempe_graph g, int32_t d, const gempe_params *p) {
@@ -523,7 +534,7 @@ extern "C" size_t gempe_loss_grad_noalloc_bytes(gempe_graph g, int32_t d, const 
         gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_noalloc_bytes: FP32 only");
         return 0;
     }
-    return gempe_ws_layout_eval(g, d, gempe_make_plan(g, d, false)).total;
+    return gempe_ws_layout_eval(g, d, noalloc_plan(g, d)).total;
 }
 
 extern "C" gempe_status gempe_loss_grad_noalloc(gempe_graph g, int32_t d, const float *X, float *grad, double *loss,
@@ -534,7 +545,7 @@ extern "C" gempe_status gempe_loss_grad_noalloc(gempe_graph g, int32_t d, const 
     if (p->precision != GEMPE_FP32)
         return gempe_fail(GEMPE_ERR_UNSUPPORTED, "loss_grad_noalloc: FP32 only (the BF16 screen needs a workspace)");
     if (!X || !grad || !loss) return gempe_fail(GEMPE_ERR_ARG, "loss_grad_noalloc: X, grad and loss are required");
-    const SweepPlan plan = gempe_make_plan(g, d, false);
+    const SweepPlan plan = noalloc_plan(g, d);
     const WsLayout L = gempe_ws_layout_eval(g, d, plan);
     if (L.total > kScratchBytes)
         return gempe_fail(GEMPE_ERR_NOMEM, "loss_grad_noalloc: the evaluation needs " + std::to_string(L.total) +

@@ -136,6 +136,12 @@ struct SweepPlan {
     bool bf16 = false;
     // one shard of the upper triangle (FP32 sweeps): items are then that shard's tiles
     int shard = 0, nshards = 1;
+    // d = 16 on the matrix cores (k_sweep_mfma16, loss and gradient only): 64-row strips
+    // against chunks of mfma_chunk column blocks of 64; the partial region holds
+    // max(items, mfma_items) slots before the edge blocks' partials
+    bool mfma = false;
+    int mfma_chunk = 8;
+    long long mfma_items = 0, mfma_grid = 0;
 };
 
 // Tiles of shard s of G over nt strips (strips p and nt-1-p paired, pair p owned by shard
@@ -197,6 +203,11 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                                   unsigned char *counters, double *loss, int64_t *hits_out,
                                   const PairParamsHost &pp, hipStream_t s, bool clear_status,
                                   const GramCtx &gc, double *red, float *wm_z = nullptr);
+// The d = 16 matrix-core sweep (sweep_mfma.hip): items of a plan with mfma_chunk, and the
+// launch over pl.items items with pl.grid workgroups.
+long long gempe_mfma_items(int n, int chunk);
+hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
+                                     const PairParamsHost &pph, hipStream_t s);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, int *chunk, hipStream_t s);

@@ -951,6 +951,7 @@ long long tiles_for(int n, int T) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr long long kPersistMaxTiles = 65536;  // 64x64 tiles: n up to ~23k
+constexpr int kMfmaMinN = 8192;                 // d = 16 sweeps on the matrix cores from this n on
 constexpr int kEdgesPerUnit = 64;
 constexpr int kRed1Blocks = 1024;  // first level of the FP64 loss reduction  // CSR entries per edge wave: one per lane
 
@@ -1009,6 +1010,23 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
     p.edge_blocks = p.D > 16 ? (int)std::max<long long>(1, ((long long)g->n + 3) / 4)
                              : (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
+
+    // d = 16 on the matrix cores for large n (loss and gradient without per-vertex extras);
+    // chunks of 8 column blocks, 16 when that keeps the grid within a launch
+    if (d == 16 && g->n >= kMfmaMinN) {
+        for (int chunk : {8, 16, 32}) {
+            const long long it = gempe_mfma_items(g->n, chunk);
+            const long long grid = (it + kXcd - 1) / kXcd * kXcd;
+            if (grid * 256 < (1LL << 32)) {
+                p.mfma = true;
+                p.mfma_chunk = chunk;
+                p.mfma_items = it;
+                p.mfma_grid = grid;
+                p.partials = std::max(p.items, it) + p.edge_blocks;
+                break;
+            }
+        }
+    }
 
     // fused-iteration plan: one workgroup per 64x64 tile, edge workgroups first
     p.persist = false;
@@ -1238,6 +1256,9 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
         TimedLaunches tl(kTkExact, s, 2);
         (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s);
         launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
+    } else if (plan.mfma) {
+        TimedLaunches tl(kTkSweep, s);
+        (void)gempe_launch_sweep_mfma16(plan, X, n, grad, partials, pph, s);
     } else {
         TimedLaunches tl(kTkSweep, s);
         launch_sweep<EX>(plan, s, X, n, d, grad, extra, partials, P);
@@ -1268,11 +1289,19 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
 }
 }  // namespace
 
-hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan, const float *X,
+hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan &plan_in, const float *X,
                                   float *grad, float *row_loss, float *partials, unsigned char *counters,
                                   double *loss, int64_t *hits_out, const PairParamsHost &pph,
                                   hipStream_t s, bool clear_status, const GramCtx &gc, double *red, float *wm_z) {
     const PairParams P = dev_params(pph);
+    // the matrix-core sweep takes plain loss-and-gradient evaluations of the whole triangle
+    // whose non-edges all lie in the pair table; the others run the vector sweep
+    SweepPlan plan = plan_in;
+    plan.mfma = plan_in.mfma && !row_loss && !wm_z && pph.table_full && plan_in.nshards <= 1;
+    if (plan.mfma) {
+        plan.items = plan_in.mfma_items;
+        plan.grid = plan_in.mfma_grid;
+    }
     const int n = g->n;
     const long long nd = (long long)n * d;
     unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counters);

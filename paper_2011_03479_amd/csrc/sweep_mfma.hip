@@ -1,0 +1,352 @@
+// FP32 all-pairs sweep for d = 16 on the matrix cores (gfx950 v_mfma_f32_16x16x4_f32).
+//
+// At d = 16 the two O(d) parts of every pair are dense contractions over a tile of rows I
+// and columns J:
+//   squared distance   r2_ij = |x_i|^2 + |x_j|^2 - 2 x_i . x_j     (Gram block X_I X_J^T)
+//   gradient           g_i += S_i x_i - sum_j cc_ij x_j,  S_i = sum_j cc_ij
+//                      g_j += T_j x_j - sum_i cc_ij x_i,  T_j = sum_i cc_ij
+// (cc_ij = (d dl/d delta)/delta, the coefficient of x_i - x_j in g_i).  Each of the three
+// products X_I X_J^T, C^T X_I and C X_J runs on FP32 MFMA (full single-precision products,
+// FP32 accumulation); the vector ALUs evaluate the pair function (the non-edge table of
+// ltab.h) between them.  Per 16 x 16 block of pairs a wave issues 4 + 4 + 4 MFMAs:
+//   - Gram: A = -2 x_I (lane (g, c) holds -2 x[i0 + c][4 kb + g], kb = 0..3), B = x_J; the
+//     accumulator starts at |x_i|^2 + |x_j|^2, so it ends holding r2 of pair
+//     (i0 + 4g + v, j0 + c) in register v of lane (g, c);
+//   - column side: B = the cc register v itself (its rows i0 + 4g + v are the contraction
+//     index), A = x_I in the layout lane (g, c) -> x[i0 + 4g + v][c];
+//   - row side: the contraction runs over j, which the Gram layout keeps on the lanes, so the
+//     cc block goes through LDS once (4 scalar writes, one 16-byte read per lane) to become
+//     the B operand, with A = x_J in the layout lane (g, c) -> x[j0 + 4g + blk][c].
+//
+// Precision.  The Gram form loses accuracy where |x_i - x_j| is small against |x_i| and
+// |x_j| (the error of r2 is a few single-precision units of |x_i|^2 + |x_j|^2, and the split
+// gradient's terms are cc |x| instead of cc |x_i - x_j|).  A pair is therefore computed from
+// the Gram only while r2 > kappa (|x_i|^2 + |x_j|^2), kappa = 1/16: its r2 then carries a
+// relative error below about 16 (d + 3) 2^-24 (typically a few 2^-24) and its split terms
+// are at most sqrt(2 / kappa) = 5.7 times the direct form's.  A pair at or below the bound
+// (a "near" pair: at N(0, 1) coordinates in 16 dimensions about one pair in 10^4) is
+// evaluated exactly instead: the difference-form squared distance and the pair function the
+// edge correction uses, its gradient added directly, and its cc left out of the MFMA
+// products.  A per-lane test of the smallest r2 of the lane's four pairs against
+// kappa (max |x_i|^2 + |x_j|^2) gates that path with one compare per four pairs.
+//
+// Work decomposition: an item is a strip of 64 rows (four waves, 16 rows each) against a
+// chunk of C column blocks of 64 (upper triangle: blocks b >= the strip's own block; the
+// diagonal block and the tails are masked).  The workgroup stages each column block in LDS,
+// every wave multiplies its 16 rows against it, the four waves' column partials meet in
+// LDS and leave with one atomic per (column, coordinate) per block; the row partials leave
+// at the end of the item.  Each item writes its FP32 loss partial to its own slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+#include "ltab.h"
+#include "pairfn.h"
+#include "tiles.h"
+
+namespace gempe {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMfLtabF4 = GEMPE_LTAB_SEGS + 1;
+constexpr int kMfLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
+constexpr int kMS = 20;                    // LDS stride of a staged column (floats)
+constexpr float kNearKappa = 1.0f / 16.0f;  // Gram pairs need r2 > kappa (|x_i|^2 + |x_j|^2)
+
+// Position of coordinate k in a staged column: lane (g, c) reads coordinates g, 4+g, 8+g,
+// 12+g of column c as one 16-byte LDS load.
+__device__ __forceinline__ int perm16(int k) { return (k & 3) * 4 + (k >> 2); }
+
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Item t -> strip I (64 rows) and column chunk J (C blocks of 64).  Strip I takes chunks
+// floor(I / C) .. nJ - 1, so its items start at I nJ - sum_{I' < I} floor(I' / C).
+__device__ inline void mfma_item(long long t, int nb, int nJ, int C, int &I, int &J) {
+    auto start = [nJ, C](long long i) -> long long {
+        const long long a = i / C, r = i - a * C;
+        return i * nJ - (C * a * (a - 1) / 2 + r * a);
+    };
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start(mid) <= t) lo = mid; else hi = mid - 1;
+    }
+    I = lo;
+    J = lo / C + (int)(t - start(lo));
+}
+
+// The exact evaluation of one near pair: the squared distance in difference form from
+// FLT_MIN and the non-edge value of the edge correction (same functions and coordinate order,
+// so an edge among the near pairs cancels bit for bit), its gradient added directly to both
+// ends.  Two passes over the coordinates (the differences recomputed for the gradient) keep
+// only a few values live inside the sweep's register-heavy loop.
+__device__ __forceinline__ float near_pair(const float *__restrict__ X, int i, int j, const float *__restrict__ ycolj,
+                                           float *__restrict__ G, const PairParams &P, const float4 *ltab,
+                                           float tko) {
+    const float *xi = X + (size_t)i * 16;
+    float r2 = 1.17549435e-38f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const float df = xi[k] - ycolj[perm16(k)];
+        r2 = __builtin_fmaf(df, df, r2);
+    }
+    float dl, cc, w;
+    nonedge_eval<false, false, true>(r2, P, ltab, tko, GEMPE_LTAB_SEGS, dl, cc, w);
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k) {
+        const float v = cc * (xi[k] - ycolj[perm16(k)]);
+        atomicAdd(&G[(size_t)i * 16 + k], v);
+        atomicAdd(&G[(size_t)j * 16 + k], -v);
+    }
+    return dl;
+}
+
+template <bool MASK>
+__device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, int r0, int j0, const float (&GA)[4],
+                                           const float (&CA)[4], const float (&ni)[4], float nimax,
+                                           const float *__restrict__ ycol, const float *__restrict__ ynrm,
+                                           float *__restrict__ tb, float *__restrict__ cp, v4f &RT, float (&S)[4],
+                                           float &loss, float *__restrict__ G, const PairParams &P,
+                                           const float4 *ltab, float tko, int g, int c) {
+    unsigned nearq = 0;  // column groups with near pairs (wave-uniform)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 gb = *reinterpret_cast<const float4 *>(ycol + (16 * q + c) * kMS + 4 * g);
+        const float GB[4] = {gb.x, gb.y, gb.z, gb.w};
+        float RA[4];
+#pragma unroll
+        for (int blk = 0; blk < 4; ++blk) RA[blk] = ycol[(16 * q + 4 * g + blk) * kMS + perm16(c)];
+        const float nj = ynrm[16 * q + c];
+        const int j = j0 + 16 * q + c;
+        v4f acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = ni[v] + nj;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = mfma(GA[kb], GB[kb], acc);
+        // pair function from the table (every non-edge tau of a Gram pair lies in it)
+        float C[4], rinv[4], f[4], dl[4];
+        unsigned off[4];
+        bool valid[4];
+        float mn = 3.0e38f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = r0 + 4 * g + v;
+            valid[v] = !MASK || (j > i && j < n && i < n);
+            const float r2 = acc[v];
+            mn = valid[v] ? fminf(mn, r2) : mn;
+            rinv[v] = hw_rsq(r2);
+            const float delta = r2 * rinv[v];
+            const float tk = __builtin_fmaf(delta, P.tk_scale, tko);
+            f[v] = __builtin_amdgcn_fractf(tk);
+            off[v] = min((unsigned)floor_to_int(tk), (unsigned)GEMPE_LTAB_SEGS) << 4;
+        }
+        float4 cf[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            cf[v] = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(ltab) + off[v]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float p = cf[v].w * f[v];
+            const float qq = cf[v].z + p;
+            const float L = __builtin_fmaf(__builtin_fmaf(qq, f[v], cf[v].y), f[v], cf[v].x);
+            const float Lf = __builtin_fmaf(__builtin_fmaf(qq, 2.0f, p), f[v], cf[v].y);
+            dl[v] = hw_exp2(L);
+            C[v] = dl[v] * (Lf * (P.slope_k * rinv[v]));
+            if (MASK) {
+                dl[v] = valid[v] ? dl[v] : 0.0f;
+                C[v] = valid[v] ? C[v] : 0.0f;
+            }
+        }
+        // near pairs (rare) are left out of the MFMA products here and evaluated exactly after
+        // the four column groups (outside this register-heavy loop)
+        if (__builtin_expect(__ballot(mn <= kNearKappa * (nimax + nj)) != 0ull, 0)) {
+            nearq |= 1u << q;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const bool nr = valid[v] && acc[v] <= kNearKappa * (ni[v] + nj);
+                dl[v] = nr ? 0.0f : dl[v];
+                C[v] = nr ? 0.0f : C[v];
+            }
+        }
+        float T = 0.0f;
+        v4f CT = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            loss += dl[v];
+            S[v] += C[v];
+            T += C[v];
+            CT = mfma(CA[v], C[v], CT);
+        }
+        // transpose the cc block through this wave's LDS slot for the row-side product
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tb[(4 * g + v) * kMS + c] = C[v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float4 ct = *reinterpret_cast<const float4 *>(tb + c * kMS + 4 * g);
+        RT = mfma(RA[0], ct.x, RT);
+        RT = mfma(RA[1], ct.y, RT);
+        RT = mfma(RA[2], ct.z, RT);
+        RT = mfma(RA[3], ct.w, RT);
+        __builtin_amdgcn_wave_barrier();
+        // this wave's column partials of the 16 columns: Col^T[4g + v][c] and T over g
+        T += __shfl_xor(T, 16, 64);
+        T += __shfl_xor(T, 32, 64);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cp[(16 * q + c) * 17 + 4 * g + v] = CT[v];
+        if (g == 0) cp[(16 * q + c) * 17 + 16] = T;
+    }
+    // the near pairs of the flagged column groups: the same Gram chain (same operands, same
+    // order, so the same r2 and the same decisions), then the exact evaluation
+    for (int q = 0; q < 4; ++q) {
+        if (!(nearq & (1u << q))) continue;
+        const float4 gb = *reinterpret_cast<const float4 *>(ycol + (16 * q + c) * kMS + 4 * g);
+        const float nj = ynrm[16 * q + c];
+        const int j = j0 + 16 * q + c;
+        v4f acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = ni[v] + nj;
+        acc = mfma(GA[0], gb.x, acc);
+        acc = mfma(GA[1], gb.y, acc);
+        acc = mfma(GA[2], gb.z, acc);
+        acc = mfma(GA[3], gb.w, acc);
+        for (int v = 0; v < 4; ++v) {
+            const int i = r0 + 4 * g + v;
+            const bool valid = !MASK || (j > i && j < n && i < n);
+            if (valid && acc[v] <= kNearKappa * (ni[v] + nj))
+                loss += near_pair(X, i, j, ycol + (16 * q + c) * kMS, G, P, ltab, tko);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ X, int n, int nb, int nJ, int C,
+                                                      long long items, long long per_xcd, float *__restrict__ G,
+                                                      float *__restrict__ partials, PairParams P) {
+    __shared__ float4 ltab[kMfLtabF4];
+    __shared__ __attribute__((aligned(16))) float ycol[64 * kMS];
+    __shared__ float ynrm[64];
+    __shared__ __attribute__((aligned(16))) float tr[4][16 * kMS];
+    __shared__ float colp[4][64 * 17];
+    __shared__ float lsum[4];
+
+    long long t = xcd_item(blockIdx.x, per_xcd);
+    if (t >= items) return;  // uniform over the workgroup
+    if (P.reverse) t = items - 1 - t;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int q = threadIdx.x; q < kMfLtabF4; q += 256) ltab[q] = reinterpret_cast<const float4 *>(kLtab)[q];
+    const float tko = table_offset(P, kMfLtabZero);
+    int I, J;
+    mfma_item(t, nb, nJ, C, I, J);
+
+    // the wave's 16 rows in the three register layouts, their squared norms
+    const int r0 = I * 64 + wave * 16;
+    float GA[4], CA[4], ni[4], S[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const int i = r0 + c;
+        GA[kb] = i < n ? -2.0f * X[(size_t)i * 16 + 4 * kb + g] : 0.0f;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = r0 + 4 * g + v;
+        CA[v] = i < n ? X[(size_t)i * 16 + c] : 0.0f;
+        ni[v] = row16_sum(CA[v] * CA[v]);
+        S[v] = 0.0f;
+    }
+    const float nimax = fmaxf(fmaxf(ni[0], ni[1]), fmaxf(ni[2], ni[3]));
+    v4f RT = {0.f, 0.f, 0.f, 0.f};
+    float loss = 0.0f;
+
+    const int b0 = max(J * C, I), b1 = min(J * C + C, nb);
+    for (int b = b0; b < b1; ++b) {
+        const int j0 = b * 64;
+        __syncthreads();  // the previous block's staged columns and partials are consumed
+        {
+            // thread t stages coordinates 4 (t % 4) .. + 3 of column t / 4 and its share of the norm
+            const int col = threadIdx.x >> 2, part = threadIdx.x & 3, j = j0 + col;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < n) v = *reinterpret_cast<const float4 *>(X + (size_t)j * 16 + 4 * part);
+            float *dst = ycol + col * kMS;
+            dst[perm16(4 * part + 0)] = v.x;
+            dst[perm16(4 * part + 1)] = v.y;
+            dst[perm16(4 * part + 2)] = v.z;
+            dst[perm16(4 * part + 3)] = v.w;
+            float s = v.x * v.x;
+            s = __builtin_fmaf(v.y, v.y, s);
+            s = __builtin_fmaf(v.z, v.z, s);
+            s = __builtin_fmaf(v.w, v.w, s);
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            if (part == 0) ynrm[col] = s;
+        }
+        __syncthreads();
+        const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
+        if (masked)
+            mfma_block<true>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, loss, G, P,
+                             ltab, tko, g, c);
+        else
+            mfma_block<false>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, loss, G, P,
+                              ltab, tko, g, c);
+        __syncthreads();
+        // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order
+        for (int k = threadIdx.x; k < 64 * 16; k += 256) {
+            const int col = k >> 4, kk = k & 15, j = j0 + col;
+            if (j < n) {
+                const float cs = (colp[0][col * 17 + kk] + colp[1][col * 17 + kk]) +
+                                 (colp[2][col * 17 + kk] + colp[3][col * 17 + kk]);
+                const float ts = (colp[0][col * 17 + 16] + colp[1][col * 17 + 16]) +
+                                 (colp[2][col * 17 + 16] + colp[3][col * 17 + 16]);
+                atomicAdd(&G[(size_t)j * 16 + kk], __builtin_fmaf(ts, ycol[col * kMS + perm16(kk)], -cs));
+            }
+        }
+    }
+    // g_i += S_i x_i - sum_j cc_ij x_j: lane (g, c) holds coordinates 4g .. 4g+3 of row r0 + c
+    // of the product; S of row r0 + 4g' + v' is the sum over the 16 lanes of DPP row g'
+    float Srow[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Srow[v] = row16_sum(S[v]);
+    const int src = (c >> 2) * 16;
+    const float s0 = __shfl(Srow[0], src, 64), s1 = __shfl(Srow[1], src, 64), s2 = __shfl(Srow[2], src, 64),
+                s3 = __shfl(Srow[3], src, 64);
+    const float si = (c & 3) == 0 ? s0 : (c & 3) == 1 ? s1 : (c & 3) == 2 ? s2 : s3;
+    const int i = r0 + c;
+    if (i < n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = 4 * g + v;
+            atomicAdd(&G[(size_t)i * 16 + k], __builtin_fmaf(si, X[(size_t)i * 16 + k], -RT[v]));
+        }
+    }
+    const float ws = wave_sum(loss);
+    if (lane == 0) lsum[wave] = ws;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[t] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
+}
+
+}  // namespace
+}  // namespace gempe
+
+using namespace gempe;
+
+long long gempe_mfma_items(int n, int chunk) {
+    const long long nb = (n + 63) / 64, nJ = (nb + chunk - 1) / chunk;
+    const long long a = nb / chunk, r = nb - a * chunk;
+    return nb * nJ - ((long long)chunk * a * (a - 1) / 2 + r * a);
+}
+
+hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
+                                     const PairParamsHost &pph, hipStream_t s) {
+    const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,   pph.tk_off,
+                       pph.slope_k, pph.r_scale,  pph.w_scale, pph.wk2,     pph.table_full, pph.reverse};
+    const int nb = (n + 63) / 64;
+    const int nJ = (nb + pl.mfma_chunk - 1) / pl.mfma_chunk;
+    const long long per = pl.grid / kXcd;
+    hipLaunchKernelGGL(k_sweep_mfma16, dim3((unsigned)pl.grid), dim3(256), 0, s, X, n, nb, nJ, pl.mfma_chunk,
+                       pl.items, per, G, partials, P);
+    return hipGetLastError();
+}

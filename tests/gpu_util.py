@@ -101,3 +101,22 @@ def check_rows(graph, G, X, rows, mu=1.5, sigma=1.0, params=None, what="", loss_
     half = 0.5 * float(np.sum(got["row_loss"]))
     assert abs(half - got["loss"]) <= 1e-5 * got["loss"], (what, half, got["loss"])
     return got, ref
+
+
+def check_rows_plain(graph, G, X, rows, mu=1.5, sigma=1.0, params=None, what="", loss_rtol=LOSS_RTOL,
+                     grad_rtol=GRAD_RTOL, grad_atol=0.0):
+    """Sampled-row parity of a plain loss-and-gradient evaluation (no per-vertex extras, the
+    call the gradient-descent loop makes): the sampled gradient rows against the oracle, and
+    the loss against the evaluation that also returns the row losses, whose rows are checked
+    against the oracle and whose halved sum is its loss."""
+    Xd = to_dev(X)
+    r = gempe.loss_grad(G, Xd, params=params)
+    torch.cuda.synchronize()
+    loss, grad = float(r.loss.item()), r.grad.double().cpu().numpy()
+    assert int(r.edge_hits.item()) == graph.m, (what, int(r.edge_hits.item()), graph.m)
+    ref = oracle.rows(X, graph.row_ptr, graph.col_idx, rows, mu, sigma)
+    assert_grad_close(grad[rows], ref["grad"], ref["abs_slope"], rtol=grad_rtol, what=what, atol=grad_atol)
+    full, _ = check_rows(graph, G, X, rows, mu, sigma, params, what + " (with row losses)", loss_rtol, grad_rtol,
+                         grad_atol)
+    assert abs(loss - full["loss"]) <= loss_rtol * abs(full["loss"]), (what, loss, full["loss"])
+    return loss, grad

@@ -19,8 +19,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (BF16_FLUSH_GRAD, BF16_GRAD_RTOL, BF16_LOSS_RTOL, LOSS_RTOL, check_rows, note,
-                      require_gpu, to_dev)
+from gpu_util import (BF16_FLUSH_GRAD, BF16_GRAD_RTOL, BF16_LOSS_RTOL, LOSS_RTOL, check_rows, check_rows_plain,
+                      note, require_gpu, to_dev)
 from paper_2011_03479_amd import gempe, synth
 
 pytestmark = pytest.mark.gpu
@@ -130,8 +130,11 @@ def test_cl1m_after_iterations(prec):
     del ws
     X5 = X.cpu().numpy()
     if prec == "fp32":
-        got, _ = check_rows(g, G, X5, rows, what="cl1m fp32 after 5 iterations")
+        # the plain evaluation (the sweep gradient descent runs) and the one with row losses
+        loss, _ = check_rows_plain(g, G, X5, rows, what="cl1m fp32 after 5 iterations")
     else:
         got, _ = _bf16_rows(g, G, X5, rows, "cl1m bf16 after 5 iterations")
-    assert abs(got["loss"] - h[-1]) <= 1e-9 * h[-1], (got["loss"], h[-1])
+        loss = got["loss"]
+    # the run's own history entry for the final iterate, within the FP32 bound
+    assert abs(loss - h[-1]) <= LOSS_RTOL * h[-1], (loss, h[-1])
     G.close()
