@@ -1011,13 +1011,14 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
                              : (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
 
-    // d = 16 on the matrix cores for large n (loss and gradient without per-vertex extras);
-    // chunks of 8 column blocks, 16 when that keeps the grid within a launch
+    // d = 16 on the matrix cores for large n (loss and gradient without per-vertex extras):
+    // the longest chunks of column blocks per item (less staging and flushing per pair; 32
+    // measured as fast as 64 or 128 on the 1M-vertex graph) that still give 16,384 items
     if (d == 16 && g->n >= kMfmaMinN) {
-        for (int chunk : {8, 16, 32}) {
+        for (int chunk : {32, 16, 8}) {
             const long long it = gempe_mfma_items(g->n, chunk);
             const long long grid = (it + kXcd - 1) / kXcd * kXcd;
-            if (grid * 256 < (1LL << 32)) {
+            if ((it >= 16384 || chunk == 8) && grid * 256 < (1LL << 32)) {
                 p.mfma = true;
                 p.mfma_chunk = chunk;
                 p.mfma_items = it;

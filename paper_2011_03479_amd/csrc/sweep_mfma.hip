@@ -31,7 +31,8 @@
 // kappa (max |x_i|^2 + |x_j|^2) gates that path with one compare per four pairs.
 //
 // Work decomposition: an item is a strip of 64 rows (four waves, 16 rows each) against a
-// chunk of C column blocks of 64 (upper triangle: blocks b >= the strip's own block; the
+// chunk of C column blocks of 64, C = 32, 16 or 8 (the largest that still gives the launch
+// 16,384 items) (upper triangle: blocks b >= the strip's own block; the
 // diagonal block and the tails are masked).  The workgroup stages each column block in LDS,
 // every wave multiplies its 16 rows against it, the four waves' column partials meet in
 // LDS and leave with one atomic per (column, coordinate) per block; the row partials leave
@@ -265,6 +266,7 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
     const int b0 = max(J * C, I), b1 = min(J * C + C, nb);
     for (int b = b0; b < b1; ++b) {
         const int j0 = b * 64;
+        float lblk = 0.0f;  // two-level loss sums: per column block, then across blocks
         __syncthreads();  // the previous block's staged columns and partials are consumed
         {
             // thread t stages coordinates 4 (t % 4) .. + 3 of column t / 4 and its share of the norm
@@ -287,11 +289,12 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
         __syncthreads();
         const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
         if (masked)
-            mfma_block<true>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, loss, G, P,
+            mfma_block<true>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, lblk, G, P,
                              ltab, tko, g, c);
         else
-            mfma_block<false>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, loss, G, P,
+            mfma_block<false>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, lblk, G, P,
                               ltab, tko, g, c);
+        loss += lblk;
         __syncthreads();
         // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order
         for (int k = threadIdx.x; k < 64 * 16; k += 256) {
