@@ -58,7 +58,8 @@ def measured_traffic(kernel: str, workload: str):
     return rec
 
 
-TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/csrc/pairfn.h",
+TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/csrc/sweep_mfma.hip",
+                   "paper_2011_03479_amd/csrc/pairfn.h",
                    "paper_2011_03479_amd/csrc/ltab.h", "paper_2011_03479_amd/csrc/erfcx_coef.h",
                    "paper_2011_03479_amd/csrc/millsq_coef.h", "paper_2011_03479_amd/csrc/tiles.h",
                    "paper_2011_03479_amd/csrc/internal.h"]
@@ -260,6 +261,10 @@ def roofline_of(w, r, steps: int):
         fpp, peak, bound = flops_per_pair(d), PEAK_FP32_TFLOPS, "alu"
         fused = w.graph.n <= 23000 and d <= 16
         name = "k_iter (fused iteration: sweep, edge pass, update)" if fused else "k_sweep_small / k_sweep_wide"
+        if d == 16 and w.graph.n >= 8192 and not fused:
+            # the squared distance and both gradient sides on FP32 MFMA (6d flops per pair),
+            # the pair function on the vector ALUs; FP32 matrix and vector peaks are the same
+            name, bound = "k_sweep_mfma16 (FP32 MFMA Gram and gradient products, VALU pair function)", "mfma"
     if not k:
         return None
     kms = k["ms_per_launch"]
@@ -339,7 +344,7 @@ def main():
     ap.add_argument("--record-traffic", default=None, metavar="DIR",
                     help="only write profiles/traffic_<workload>.json from the rocprofv3 --pmc runs under "
                          "DIR (no GPU needed); --traffic-kernel names the kernel")
-    ap.add_argument("--traffic-kernel", default="gempe::k_sweep_small<16, 2, 4, 0>")
+    ap.add_argument("--traffic-kernel", default="gempe::k_sweep_mfma16")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)

@@ -36,7 +36,9 @@
 // diagonal block and the tails are masked).  The workgroup stages each column block in LDS,
 // every wave multiplies its 16 rows against it, the four waves' column partials meet in
 // LDS and leave with one atomic per (column, coordinate) per block; the row partials leave
-// at the end of the item.  Each item writes its FP32 loss partial to its own slot.
+// at the end of the item.  Each item writes its FP32 loss partial to its own slot.  Items
+// run chunk by chunk (all strips of a column chunk, then the next chunk), so the column data
+// comes from L2 and each strip's 64 rows are read once per chunk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -64,20 +66,23 @@ __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Item t -> strip I (64 rows) and column chunk J (C blocks of 64).  Strip I takes chunks
-// floor(I / C) .. nJ - 1, so its items start at I nJ - sum_{I' < I} floor(I' / C).
+// Item t -> column chunk J (C blocks of 64) and strip I (64 rows), chunk-major: chunk J is
+// needed by strips 0 .. min(nb, (J + 1) C) - 1, so the items of one chunk are consecutive and
+// the workgroups an XCD runs together (consecutive items, see xcd_item) share that chunk's
+// columns in the XCD's L2.  Chunks J < Jf = floor(nb / C) have (J + 1) C strips, the rest nb.
 __device__ inline void mfma_item(long long t, int nb, int nJ, int C, int &I, int &J) {
-    auto start = [nJ, C](long long i) -> long long {
-        const long long a = i / C, r = i - a * C;
-        return i * nJ - (C * a * (a - 1) / 2 + r * a);
+    const long long Jf = nb / C;
+    auto start = [nb, C, Jf](long long j) -> long long {
+        const long long m = j < Jf ? j : Jf;
+        return C * m * (m + 1) / 2 + (j - m) * nb;
     };
-    int lo = 0, hi = nb - 1;
+    int lo = 0, hi = nJ - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (start(mid) <= t) lo = mid; else hi = mid - 1;
     }
-    I = lo;
-    J = lo / C + (int)(t - start(lo));
+    J = lo;
+    I = (int)(t - start(lo));
 }
 
 // The exact evaluation of one near pair: the squared distance in difference form from
@@ -224,6 +229,8 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
     }
 }
 
+}  // namespace
+
 __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ X, int n, int nb, int nJ, int C,
                                                       long long items, long long per_xcd, float *__restrict__ G,
                                                       float *__restrict__ partials, PairParams P) {
@@ -331,7 +338,6 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
     if (threadIdx.x == 0) partials[t] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
 }
 
-}  // namespace
 }  // namespace gempe
 
 using namespace gempe;
