@@ -1266,13 +1266,18 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     }
     TimedLaunches tl(kTkEdges, s);
     float *epart = partials + plan.items;
-    if (plan.D > 16) {
-        // wide: one wave per CSR row (also writes the partial of rows without edges)
+    if (plan.D > 16 || plan.bf16) {
+        // wide, and every BF16 plan: one wave per CSR row (also writes the partial of rows
+        // without edges), with the squared distance (group16_sqdist) and the closed-form pair
+        // function of the BF16 path's exact near-pair pass, so a near edge's non-edge term
+        // cancels there bit for bit
 #define GEMPE_EDGES_ROWS(DD)                                                                              \
     hipLaunchKernelGGL((k_edges_rows<DD, EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr, \
                        g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, hits, P,    \
                        plan.T, plan.nt, plan.shard, plan.nshards)
-        if (plan.D == 32)
+        if (plan.D == 16)
+            GEMPE_EDGES_ROWS(16);
+        else if (plan.D == 32)
             GEMPE_EDGES_ROWS(32);
         else if (plan.D == 64)
             GEMPE_EDGES_ROWS(64);

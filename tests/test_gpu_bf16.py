@@ -6,7 +6,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import (BF16_FLUSH_GRAD, BF16_GRAD_RTOL, BF16_LOSS_RTOL, check_full, check_rows, gpu_loss_grad, note, require_gpu,
+from gpu_util import (BF16_FLUSH_GRAD, BF16_GRAD_RTOL, BF16_LOSS_RTOL, assert_grad_close, check_full, check_rows,
+                      gpu_loss_grad, note, require_gpu,
                       to_dev)
 from paper_2011_03479_amd import gempe, synth
 
@@ -120,3 +121,39 @@ def test_bf16_tall_strips_clusters(n, d):
     G = gempe.Graph(n, g.row_ptr, g.col_idx)
     check_rows(g, G, X, rows, params=gempe.params_default(**BF16), what=f"bf16 tall n{n} d{d}",
                loss_rtol=BF16_LOSS_RTOL, grad_rtol=BF16_GRAD_RTOL, grad_atol=(n - 1) * BF16_FLUSH_GRAD)
+
+
+def test_bf16_d16_near_edges_cancel():
+    """BF16 at d = 16: a 16-vertex clique packed into a ball of radius 0.03 (every pair a
+    near edge, dl+ ~ 0.1 bit, dl- ~ 3.9 bits) plus far vertices.  The near-pair pass adds
+    each edge's non-edge term and the edge pass subtracts it; computed with the same squared
+    distance and pair function they cancel bit for bit, leaving only the FP32 rounding of
+    dl+ - dl- (~2e-7 relative of 3.9 bits per pair), well inside 5e-6 of the loss.  A
+    non-edge term from another pair function (the table's ~1e-6 relative error) would move
+    the loss by ~2e-5."""
+    n = 300
+    rng = np.random.default_rng(41)
+    X = rng.standard_normal((n, 16)) * 3.0
+    X[:16] = rng.standard_normal((16, 16)) * (0.03 / 4.0)
+    X = X.astype(np.float32)
+    cl = np.arange(16)
+    uu, vv = np.meshgrid(cl, cl)
+    keep = uu < vv
+    g = synth.csr_from_edges(n, uu[keep], vv[keep])
+    note("bf16 d16 near clique")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    got = gpu_loss_grad(G, X, params=gempe.params_default(**BF16))
+    ref = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_abs_slope=True)
+    assert got["edge_hits"] == g.m == 120
+    # the clique's own pairs carry the loss that matters here: compare its share
+    ref_far = oracle.loss_grad(X[16:], synth.csr_from_edges(n - 16, np.zeros(0, np.int64),
+                                                            np.zeros(0, np.int64)).row_ptr,
+                               np.zeros(0, np.int32), want_grad=False)["loss"]
+    clique_gpu = got["loss"] - ref_far
+    clique_ref = ref["loss"] - ref_far
+    assert abs(clique_gpu - clique_ref) <= 5e-6 * ref["loss"], (clique_gpu, clique_ref, ref["loss"])
+    # the stated BF16 gradient bound (the far vertices' pairs are all flushed, < 2e-18 each)
+    assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], rtol=BF16_GRAD_RTOL, what="bf16 d16 near clique",
+                      atol=(n - 1) * BF16_FLUSH_GRAD)
+    # the clique's vertices, whose pairs are all near edges, meet the FP32 bound
+    assert_grad_close(got["grad"][:16], ref["grad"][:16], ref["abs_slope"][:16], what="bf16 d16 clique vertices")
