@@ -434,12 +434,20 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                                                     const int *__restrict__ count, gempe::PairParams P,
                                                     float *__restrict__ G, float *__restrict__ extra,
                                                     float *__restrict__ partials,
-                                                    unsigned char *__restrict__ dense) {
+                                                    unsigned char *__restrict__ dense, int all_dense_ok) {
     __shared__ int near[4][kSparseNear];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lrow = lane & 31, lk = (lane >> 5) * 8;
     const int cnt = *count;
+    // when the dense pass can take any flagged tile (all_dense_ok) and most tiles are flagged
+    // (d = 16 from a spread start: nearly every pair lies within the near distance), every
+    // flagged tile goes to it directly instead of being recomputed here only to be found dense
+    if (all_dense_ok && 2LL * cnt > nb64 * (nb64 + 1) / 2) {
+        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (long long)gridDim.x * 256)
+            dense[q] = 1;
+        return;
+    }
     for (int q = blockIdx.x * 4 + wave; q < cnt; q += gridDim.x * 4) {
         int R64, C64;
         gempe::tile_of(list[q], (int)nb64, R64, C64);
@@ -606,13 +614,13 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
 namespace {
 template <int EX>
 void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc, const gempe::PairParams &P,
-                          float *G, float *extra, float *partials, hipStream_t s) {
+                          float *G, float *extra, float *partials, hipStream_t s, int all_dense_ok) {
     const long long nb64 = (g->n + 63) / 64;
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(gc.xb);
     const dim3 grid(kNearTileGrid), block(256);
 #define GEMPE_NEAR(DD)                                                                                     \
     hipLaunchKernelGGL((k_near_tiles<DD, EX>), grid, block, 0, s, xb, X, gc.nrm, gc.smax128, g->n, nb64,  \
-                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense)
+                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense, all_dense_ok)
     switch (d) {
         case 16: GEMPE_NEAR(16); break;
         case 32: GEMPE_NEAR(32); break;
@@ -629,14 +637,14 @@ void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const G
 
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &h, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s) {
+                                   hipStream_t s, bool all_dense_ok) {
     const gempe::PairParams P{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
                               h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full, 0};
     if (ex == 2)
-        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s);
+        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
     else if (ex == 1)
-        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s);
+        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
     else
-        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s);
+        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
     return hipGetLastError();
 }

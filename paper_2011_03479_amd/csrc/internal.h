@@ -208,13 +208,18 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
 long long gempe_mfma_items(int n, int chunk);
 hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
                                      const PairParamsHost &pph, hipStream_t s);
+// The BF16 path's exact pass over its densely flagged tiles at d = 16, on the matrix cores.
+hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, int n, const GramCtx &gc, float *G,
+                                          float *partials, const PairParamsHost &pph, hipStream_t s);
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, int *chunk, hipStream_t s);
 // Sparse exact pass over the flagged tiles (gram.hip); ex: 0 none, 1 row loss, 2 WM z.
+// all_dense_ok: the dense pass can take any flagged tile; when more than half of the tiles
+// are flagged, all of them are then marked dense without being recomputed here.
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &pp, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s);
+                                   hipStream_t s, bool all_dense_ok = false);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s);
 // Continuous batching of fused iterations (sweep.hip): one table row per job.

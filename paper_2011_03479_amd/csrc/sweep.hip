@@ -1255,8 +1255,15 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     if (plan.bf16) {
         // near pairs of sparsely flagged tiles exactly, the dense tiles by the LDS tile pass
         TimedLaunches tl(kTkExact, s, 2);
-        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s);
-        launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
+        // at d = 16 the dense tiles of a plain evaluation go to the matrix cores (FP32 Gram
+        // with the exact path for near pairs); otherwise, and for per-vertex extras, the LDS
+        // tile pass
+        const bool mf16 = EX == kExNone && d == 16 && pph.table_full;
+        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, mf16);
+        if (mf16)
+            (void)gempe_launch_sweep_mfma16_list(plan, X, n, gc, grad, partials, pph, s);
+        else
+            launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
     } else if (plan.mfma) {
         TimedLaunches tl(kTkSweep, s);
         (void)gempe_launch_sweep_mfma16(plan, X, n, grad, partials, pph, s);

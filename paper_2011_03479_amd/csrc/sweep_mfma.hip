@@ -57,6 +57,7 @@ constexpr int kMfLtabF4 = GEMPE_LTAB_SEGS + 1;
 constexpr int kMfLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
 constexpr int kMS = 20;                    // LDS stride of a staged column (floats)
 constexpr float kNearKappa = 1.0f / 16.0f;  // Gram pairs need r2 > kappa (|x_i|^2 + |x_j|^2)
+constexpr int kListSlots = 128;             // list slots per workgroup in the BF16 path's dense pass
 
 // Position of coordinate k in a staged column: lane (g, c) reads coordinates g, 4+g, 8+g,
 // 12+g of column c as one 16-byte LDS load.
@@ -111,13 +112,16 @@ __device__ __forceinline__ float near_pair(const float *__restrict__ X, int i, i
     return dl;
 }
 
-template <bool MASK>
+// One 64-column block against the wave's 16 rows.  MASK: the diagonal block or a tail (only
+// pairs i < j < n, i < n count).  FLUSH: pairs with r2 >= far2 add exactly 0 (the BF16 path's
+// far non-edges, flushed as its screen flushes them).
+template <bool MASK, bool FLUSH>
 __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, int r0, int j0, const float (&GA)[4],
                                            const float (&CA)[4], const float (&ni)[4], float nimax,
                                            const float *__restrict__ ycol, const float *__restrict__ ynrm,
                                            float *__restrict__ tb, float *__restrict__ cp, v4f &RT, float (&S)[4],
                                            float &loss, float *__restrict__ G, const PairParams &P,
-                                           const float4 *ltab, float tko, int g, int c) {
+                                           const float4 *ltab, float tko, float far2, int g, int c) {
     unsigned nearq = 0;  // column groups with near pairs (wave-uniform)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -165,6 +169,11 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
             if (MASK) {
                 dl[v] = valid[v] ? dl[v] : 0.0f;
                 C[v] = valid[v] ? C[v] : 0.0f;
+            }
+            if (FLUSH) {
+                const bool far = acc[v] >= far2;
+                dl[v] = far ? 0.0f : dl[v];
+                C[v] = far ? 0.0f : C[v];
             }
         }
         // near pairs (rare) are left out of the MFMA products here and evaluated exactly after
@@ -229,28 +238,24 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
     }
 }
 
-}  // namespace
+// LDS of one matrix-core workgroup.
+struct MfLds {
+    float4 ltab[kMfLtabF4];
+    __attribute__((aligned(16))) float ycol[64 * kMS];
+    float ynrm[64];
+    __attribute__((aligned(16))) float tr[4][16 * kMS];
+    float colp[4][64 * 17];
+    float lsum[4];
+};
 
-__global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ X, int n, int nb, int nJ, int C,
-                                                      long long items, long long per_xcd, float *__restrict__ G,
-                                                      float *__restrict__ partials, PairParams P) {
-    __shared__ float4 ltab[kMfLtabF4];
-    __shared__ __attribute__((aligned(16))) float ycol[64 * kMS];
-    __shared__ float ynrm[64];
-    __shared__ __attribute__((aligned(16))) float tr[4][16 * kMS];
-    __shared__ float colp[4][64 * 17];
-    __shared__ float lsum[4];
-
-    long long t = xcd_item(blockIdx.x, per_xcd);
-    if (t >= items) return;  // uniform over the workgroup
-    if (P.reverse) t = items - 1 - t;
+// Strip I (64 rows, four waves of 16) against column blocks [b0, b1): stage each block, the
+// three products per 16 x 16 block, the column partials per block, the row partials at the
+// end.  Returns the workgroup's FP32 loss in thread 0.
+template <bool FLUSH>
+__device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, int b1, float *__restrict__ G,
+                            const PairParams &P, float tko, float far2, MfLds &L) {
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    for (int q = threadIdx.x; q < kMfLtabF4; q += 256) ltab[q] = reinterpret_cast<const float4 *>(kLtab)[q];
-    const float tko = table_offset(P, kMfLtabZero);
-    int I, J;
-    mfma_item(t, nb, nJ, C, I, J);
-
     // the wave's 16 rows in the three register layouts, their squared norms
     const int r0 = I * 64 + wave * 16;
     float GA[4], CA[4], ni[4], S[4];
@@ -270,7 +275,6 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
     v4f RT = {0.f, 0.f, 0.f, 0.f};
     float loss = 0.0f;
 
-    const int b0 = max(J * C, I), b1 = min(J * C + C, nb);
     for (int b = b0; b < b1; ++b) {
         const int j0 = b * 64;
         float lblk = 0.0f;  // two-level loss sums: per column block, then across blocks
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
             const int col = threadIdx.x >> 2, part = threadIdx.x & 3, j = j0 + col;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < n) v = *reinterpret_cast<const float4 *>(X + (size_t)j * 16 + 4 * part);
-            float *dst = ycol + col * kMS;
+            float *dst = L.ycol + col * kMS;
             dst[perm16(4 * part + 0)] = v.x;
             dst[perm16(4 * part + 1)] = v.y;
             dst[perm16(4 * part + 2)] = v.z;
@@ -291,27 +295,27 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
             s = __builtin_fmaf(v.w, v.w, s);
             s += __shfl_xor(s, 1, 64);
             s += __shfl_xor(s, 2, 64);
-            if (part == 0) ynrm[col] = s;
+            if (part == 0) L.ynrm[col] = s;
         }
         __syncthreads();
         const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
         if (masked)
-            mfma_block<true>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, lblk, G, P,
-                             ltab, tko, g, c);
+            mfma_block<true, FLUSH>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT, S,
+                                    lblk, G, P, L.ltab, tko, far2, g, c);
         else
-            mfma_block<false>(X, n, r0, j0, GA, CA, ni, nimax, ycol, ynrm, tr[wave], colp[wave], RT, S, lblk, G, P,
-                              ltab, tko, g, c);
+            mfma_block<false, FLUSH>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT,
+                                     S, lblk, G, P, L.ltab, tko, far2, g, c);
         loss += lblk;
         __syncthreads();
         // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order
         for (int k = threadIdx.x; k < 64 * 16; k += 256) {
             const int col = k >> 4, kk = k & 15, j = j0 + col;
             if (j < n) {
-                const float cs = (colp[0][col * 17 + kk] + colp[1][col * 17 + kk]) +
-                                 (colp[2][col * 17 + kk] + colp[3][col * 17 + kk]);
-                const float ts = (colp[0][col * 17 + 16] + colp[1][col * 17 + 16]) +
-                                 (colp[2][col * 17 + 16] + colp[3][col * 17 + 16]);
-                atomicAdd(&G[(size_t)j * 16 + kk], __builtin_fmaf(ts, ycol[col * kMS + perm16(kk)], -cs));
+                const float cs = (L.colp[0][col * 17 + kk] + L.colp[1][col * 17 + kk]) +
+                                 (L.colp[2][col * 17 + kk] + L.colp[3][col * 17 + kk]);
+                const float ts = (L.colp[0][col * 17 + 16] + L.colp[1][col * 17 + 16]) +
+                                 (L.colp[2][col * 17 + 16] + L.colp[3][col * 17 + 16]);
+                atomicAdd(&G[(size_t)j * 16 + kk], __builtin_fmaf(ts, L.ycol[col * kMS + perm16(kk)], -cs));
             }
         }
     }
@@ -333,9 +337,68 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
         }
     }
     const float ws = wave_sum(loss);
-    if (lane == 0) lsum[wave] = ws;
+    if (lane == 0) L.lsum[wave] = ws;
     __syncthreads();
-    if (threadIdx.x == 0) partials[t] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
+    return (L.lsum[0] + L.lsum[1]) + (L.lsum[2] + L.lsum[3]);
+}
+
+__device__ __forceinline__ void stage_table(MfLds &L) {
+    for (int q = threadIdx.x; q < kMfLtabF4; q += 256) L.ltab[q] = reinterpret_cast<const float4 *>(kLtab)[q];
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ X, int n, int nb, int nJ, int C,
+                                                      long long items, long long per_xcd, float *__restrict__ G,
+                                                      float *__restrict__ partials, PairParams P) {
+    __shared__ MfLds L;
+    long long t = xcd_item(blockIdx.x, per_xcd);
+    if (t >= items) return;  // uniform over the workgroup
+    if (P.reverse) t = items - 1 - t;
+    stage_table(L);  // the strip's first barrier orders it before any use
+    int I, J;
+    mfma_item(t, nb, nJ, C, I, J);
+    const float l = mfma_strip<false>(X, n, I, max(J * C, I), min(J * C + C, nb), G, P,
+                                      table_offset(P, kMfLtabZero), 0.0f, L);
+    if (threadIdx.x == 0) partials[t] = l;
+}
+
+// The exact FP32 pass of the BF16 path at d = 16 over the densely flagged 64 x 64 tiles of
+// its screen (list[0..*count) in increasing order, dense[q] set; partial slot q belongs to
+// list[q]), on the matrix cores: the pairs at or beyond the far distance add 0 as the
+// screen's unflagged pairs do, the near pairs take the exact path.
+__global__ __launch_bounds__(256) void k_sweep_mfma16_list(const float *__restrict__ X, int n, int nb,
+                                                           const int *__restrict__ list,
+                                                           const int *__restrict__ count,
+                                                           const unsigned char *__restrict__ dense,
+                                                           float *__restrict__ G, float *__restrict__ partials,
+                                                           PairParams P, float far2) {
+    __shared__ MfLds L;
+    stage_table(L);
+    const float tko = table_offset(P, kMfLtabZero);
+    const int cnt = *count;
+    // workgroup w owns slots [S w, S w + S), S = kListSlots (and the same range one grid further on); a
+    // run of dense slots holding consecutive tiles of one strip is one strip call (rows loaded
+    // and flushed once), its loss in the run's first slot and 0 in the others
+    for (int base = blockIdx.x * kListSlots; base < cnt; base += gridDim.x * kListSlots) {
+        const int end = min(base + kListSlots, cnt);
+        for (int q = base; q < end;) {
+            if (!dense[q]) {  // uniform: finished by the sparse pass
+                ++q;
+                continue;
+            }
+            int I, J;
+            tile_of(list[q], nb, I, J);
+            int r = q + 1;
+            while (r < end && dense[r] && list[r] == list[r - 1] + 1 && J + (r - q) < nb) ++r;
+            const float l = mfma_strip<true>(X, n, I, J, J + (r - q), G, P, tko, far2, L);
+            if (threadIdx.x == 0) {
+                partials[q] = l;
+                for (int z = q + 1; z < r; ++z) partials[z] = 0.0f;
+            }
+            q = r;
+        }
+    }
 }
 
 }  // namespace gempe
@@ -357,5 +420,17 @@ hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n,
     const long long per = pl.grid / kXcd;
     hipLaunchKernelGGL(k_sweep_mfma16, dim3((unsigned)pl.grid), dim3(256), 0, s, X, n, nb, nJ, pl.mfma_chunk,
                        pl.items, per, G, partials, P);
+    return hipGetLastError();
+}
+
+hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, int n, const GramCtx &gc, float *G,
+                                          float *partials, const PairParamsHost &pph, hipStream_t s) {
+    const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,   pph.tk_off,
+                       pph.slope_k, pph.r_scale,  pph.w_scale, pph.wk2,     pph.table_full, pph.reverse};
+    const int nb = (n + 63) / 64;
+    const unsigned grid =
+        (unsigned)std::max<long long>(1, std::min<long long>((pl.items + kListSlots - 1) / kListSlots, 8192));
+    hipLaunchKernelGGL(k_sweep_mfma16_list, dim3(grid), dim3(256), 0, s, X, n, nb, gc.list, gc.count, gc.dense, G,
+                       partials, P, gc.theta0 * gc.theta0);
     return hipGetLastError();
 }
