@@ -8,7 +8,7 @@ finite check, and the update X <- X - eta G.  The default workload is the large 
 sweep: a Chung-Lu power-law graph with n = 1,000,000 vertices, mean degree 20 and degree
 exponent 2.3 (about 1e7 edges), d = 16, FP32; the same graph with the BF16 MFMA Gram screen
 is measured in the same run under `variants`, and the other workloads (the drawing-sized
-graph at d = 2, the SBM at d = 128 in BF16) under `extras`.  Prints one JSON line with
+graph at d = 2, the SBM at d = 128 in BF16 and in FP32) under `extras`.  Prints one JSON line with
 pairs/s (unordered pairs x iterations / time), the roofline figures of the dominant
 kernel, timed with HIP events on the stream it runs on, the FP64 CPU oracle timed on the
 host on a bounded sample of rows, and the serving mix.
@@ -318,10 +318,11 @@ def roofline_of(w, r, steps: int):
         fpp, peak, bound = flops_per_pair(d), PEAK_FP32_TFLOPS, "alu"
         fused = w.graph.n <= 23000 and d <= 16
         name = "k_iter (fused iteration: sweep, edge pass, update)" if fused else "k_sweep_small / k_sweep_wide"
-        if d == 16 and w.graph.n >= 8192 and not fused:
+        if (d == 16 and w.graph.n >= 8192 and not fused) or (d in (32, 64, 128) and w.graph.n >= 4096):
             # the squared distance and both gradient sides on FP32 MFMA (6d flops per pair),
             # the pair function on the vector ALUs; FP32 matrix and vector peaks are the same
-            name, bound = "k_sweep_mfma16 (FP32 MFMA Gram and gradient products, VALU pair function)", "mfma"
+            kern = "k_sweep_mfma16" if d == 16 else f"k_sweep_mfma_wide<{d}>"
+            name, bound = f"{kern} (FP32 MFMA Gram and gradient products, VALU pair function)", "mfma"
     if not k:
         return None
     kms = k["ms_per_launch"]
@@ -475,7 +476,7 @@ def main():
             print(f"# cl1m_bf16: {rb['ms'] / args.variant_steps:.3f} ms/iteration", file=sys.stderr, flush=True)
         del w
         result["extras"] = {}
-        for name, st, wu in (("cl3400", 1000, 20), ("sbm100k", 20, 2)):
+        for name, st, wu in (("cl3400", 1000, 20), ("sbm100k", 20, 2), ("sbm100k_fp32", 3, 1)):
             we = synth.workload(name)
             re_ = gd_run(we, st, wu)
             result["extras"][name] = summary(we, re_, st, wu)

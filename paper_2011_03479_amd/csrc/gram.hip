@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "ltab_stage.h"
 #include "pairfn.h"
 #include "tiles.h"
 
@@ -448,6 +449,12 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
             dense[q] = 1;
         return;
     }
+    // d = 16 takes the non-edge value from the table, as the dense pass and the edge pass do
+    __shared__ float4 ltab[D == 16 ? gempe::kLtabF4 : 1];
+    if (D == 16) {
+        gempe::stage_ltab(ltab);
+        __syncthreads();
+    }
     for (int q = blockIdx.x * 4 + wave; q < cnt; q += gridDim.x * 4) {
         int R64, C64;
         gempe::tile_of(list[q], (int)nb64, R64, C64);
@@ -536,7 +543,11 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                 for (int k = 0; k < C; ++k) xr[k] = X[(size_t)i * D + sub + 16 * k];
                 const float r2 = gempe::group16_sqdist<C>(xr, X + (size_t)j * D, sub, D, df);
                 float dl, cc, w = 0.0f;
-                gempe::pair_eval_t<EX == 2>(r2, 1.0f, P, dl, cc, w);
+                if (D == 16)
+                    gempe::nonedge_eval<EX == 2>(r2 + gempe::kFltMin, P, ltab, gempe::table_offset(P, gempe::kLtabZero),
+                                                 gempe::kLtabSegs, dl, cc, w);
+                else
+                    gempe::pair_eval_t<EX == 2>(r2, 1.0f, P, dl, cc, w);
                 if (valid) {
 #pragma unroll
                     for (int k = 0; k < C; ++k) {

@@ -136,7 +136,7 @@ struct SweepPlan {
     bool bf16 = false;
     // one shard of the upper triangle (FP32 sweeps): items are then that shard's tiles
     int shard = 0, nshards = 1;
-    // d = 16 on the matrix cores (k_sweep_mfma16, loss and gradient only): 64-row strips
+    // d = 16, 32, 64, 128 on the matrix cores (loss and gradient only): 64-row strips
     // against chunks of mfma_chunk column blocks of 64; the partial region holds
     // max(items, mfma_items) slots before the edge blocks' partials
     bool mfma = false;
@@ -208,6 +208,9 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
 long long gempe_mfma_items(int n, int chunk);
 hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
                                      const PairParamsHost &pph, hipStream_t s);
+// The same for d = 32, 64, 128 (k_sweep_mfma_wide<d>).
+hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
+                                        const PairParamsHost &pph, hipStream_t s);
 // The BF16 path's exact pass over its densely flagged tiles at d = 16, on the matrix cores.
 hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, int n, const GramCtx &gc, float *G,
                                           float *partials, const PairParamsHost &pph, hipStream_t s);

@@ -49,6 +49,14 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kSqrt1_2 = 0.70710678118654752f;
 constexpr float kSqrt2 = 1.41421356237309505f;
 constexpr float kFltMin = 1.17549435e-38f;
+// The hardware exp2 returns 0 for results below 2^-126 (FP32's smallest normal).  A far
+// non-edge (tau beyond about 13.2; common at d = 128 from a spread start) has dl and cc in
+// that range, and a vertex with only far pairs owes its whole gradient to them, so both
+// pair functions evaluate exp2 on a range where its result is normal and scale back with a
+// multiplication, which rounds into the subnormals as IEEE arithmetic does.  The staged
+// one-gather table holds log2 dl + kTabLogScale (its c0 raised when it is staged).
+constexpr float kTabLogScale = 32.0f;
+constexpr float kTabUnscale = 0x1p-32f;
 
 __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -60,7 +68,10 @@ __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf
 // of the parabola match dl at the current distance), w = dl''/2 = R (R + tau) / (2 sigma^2
 // ln 2).  For tau < 0, R + tau = R q(-tau) with q(t) = 1 - t M(t) (M the Mills ratio) from
 // millsq_coef.h, so far edges (R + tau -> 1/|tau|) keep full relative accuracy.
-template <bool W>
+// TAIL = false: exp(-u^2) below 2^-126 (tau beyond about 13.2) is taken as 0, for callers
+// that give such pairs 0 anyway (the BF16 path's far flush); the bits of every other pair
+// are the same for both values of TAIL.
+template <bool W, bool TAIL = true>
 __device__ __forceinline__ void pair_eval_t(float r2, float a, const PairParams &P, float &dl, float &cc,
                                             float &w) {
     // FLT_MIN keeps rsq finite at r2 = 0 and leaves every r2 > 2^-102 unchanged; NaN and
@@ -81,7 +92,15 @@ __device__ __forceinline__ void pair_eval_t(float r2, float a, const PairParams 
     for (int k = GEMPE_ERFCX_NCOEF - 2; k >= 0; --k) f = __builtin_fmaf(f, y, kErfcxHalfCoef[k]);
     float h = f * (A * q);                          // erfcx(u) / 2
     float nu2l = tau * (tau * (-0.5f * kLog2e));    // -u^2 log2(e)
-    float E = hw_exp2(nu2l);                        // exp(-u^2)
+    float E;                                        // exp(-u^2)
+    if (TAIL) {
+        // below 2^-64 the exponent is raised by 64 (exactly: nu2l is then a multiple of its
+        // ulp of at least 2^-17) and the result scaled back
+        const bool tiny = nu2l < -64.0f;
+        E = hw_exp2(tiny ? nu2l + 64.0f : nu2l) * (tiny ? 0x1p-64f : 1.0f);
+    } else {
+        E = hw_exp2(nu2l);
+    }
     float q_small = h * E;                          // Phi(-|tau|)
     float one_m = 1.0f - q_small;                   // Phi(|tau|), rounded
     bool neg = tau < 0.0f;
@@ -116,9 +135,10 @@ __device__ __forceinline__ void pair_nonedge(float r2, const PairParams &P, floa
 
 // ------------------------------------------------------------------------------------
 // Non-edge pair from the piecewise-cubic table of L = log2 dl(tau) (ltab.h), staged in LDS
-// as one float4 {c0, c1, c2, c3} per segment of width 1/16 in tau:
+// as one float4 {c0 + kTabLogScale, c1, c2, c3} per segment of width 1/16 in tau:
 //   16 tau + zero = tk_scale delta + tko,  segment = floor of that,  f = its fraction
 //   dl = 2^(c0 + f(c1 + f(c2 + f c3))),  d dl/d delta = dl slope_k (c1 + f(2 c2 + 3 c3 f))
+// with the exp2 taken 2^32 times larger and the results scaled back (see kTabLogScale)
 // (tko = tk_off + zero from table_offset, zero = the segment of tau = 0).  Two
 // transcendentals (rsq, exp2) instead of five and one 16-byte LDS gather per pair.  r2
 // must be positive: the sweeps' squared distances start from FLT_MIN (sqdist_eps), which
@@ -155,13 +175,15 @@ __device__ __forceinline__ bool pair_nonedge_tab(float r2, const PairParams &P, 
     // L and dL/df share p = c3 f, q = c2 + p:  L = c0 + f (c1 + f q),  dL/df = c1 + f (2q + p)
     const float p = c.w * f;
     const float q = c.z + p;
-    const float L = __builtin_fmaf(__builtin_fmaf(q, f, c.y), f, c.x);
+    const float L = __builtin_fmaf(__builtin_fmaf(q, f, c.y), f, c.x);  // log2 dl + kTabLogScale
     const float Lf = __builtin_fmaf(__builtin_fmaf(q, 2.0f, p), f, c.y);
-    dl = hw_exp2(L);
-    cc = dl * (Lf * (P.slope_k * rinv));  // (d dl / d delta) / delta, one multiply after the exp2
+    const float dls = hw_exp2(L);  // 2^32 dl, normal down to dl = 2^-158
+    const float slope = P.slope_k * kTabUnscale;
+    dl = dls * kTabUnscale;
+    cc = dls * (Lf * (slope * rinv));  // (d dl / d delta) / delta, one multiply after the exp2
     // w = R (R + tau) / (2 sigma^2 ln 2) with R = -sigma ln2 c1:  w = c1 (ln2/2 c1 - tau/(2 sigma))
     if (W) {
-        const float c1 = (dl * Lf) * P.slope_k;  // d dl / d delta
+        const float c1 = (dls * Lf) * slope;  // d dl / d delta
         w = c1 * __builtin_fmaf(0.34657359028f, c1, __builtin_fmaf(delta, P.tk_scale, P.tk_off) * P.wk2);
     }
     return ok;

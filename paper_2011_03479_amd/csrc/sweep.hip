@@ -35,21 +35,10 @@
 
 #include "internal.h"
 #include "pairfn.h"
-#include "ltab.h"
+#include "ltab_stage.h"
 #include "tiles.h"
 
 namespace gempe {
-
-// The non-edge table (ltab.h), one float4 per segment, staged into LDS by every workgroup
-// that sweeps or corrects edges for d <= 16.
-constexpr int kLtabF4 = GEMPE_LTAB_SEGS + 1;  // the segments and the all-zero one past them
-constexpr int kLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
-constexpr unsigned kLtabSegs = GEMPE_LTAB_SEGS;
-
-__device__ __forceinline__ void stage_ltab(float4 *dst) {
-    const float4 *src = reinterpret_cast<const float4 *>(kLtab);
-    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) dst[q] = src[q];
-}
 
 // The two-float4 form (pair_nonedge_tab2) of the same table: 2 kLtabF4 float4.
 __device__ __forceinline__ void stage_ltab2(float4 *dst, float slope_k) {
@@ -284,10 +273,13 @@ __global__ __launch_bounds__(64 * W) void k_sweep_small(const float *__restrict_
 // ------------------------------------------------------------------------------------
 // FLUSH (BF16 screen's exact pass only): a step whose 64 exact distances all satisfy
 // delta^2 >= far2 = (mu + near_k sigma)^2 skips the pair function and the gradient: those
-// pairs are far non-edges, flushed exactly as the screen flushes them.
+// pairs are far non-edges, flushed exactly as the screen flushes them.  D = 16 (the BF16
+// path's dense tiles with per-vertex extras) takes the non-edge value from the staged table
+// ltab, as that path's other passes do; wider tiles the closed form.
 template <int D, int EX, bool FLUSH>
 __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int J, float *__restrict__ G,
-                           float *__restrict__ rowloss, const PairParams &P, float *lds, float far2) {
+                           float *__restrict__ rowloss, const PairParams &P, float *lds, float far2,
+                           const float4 *ltab) {
     constexpr int S = D + 1;  // padded stride: lane-private rows hit distinct banks
     float *xr = lds;           // rows    [64][S]
     float *gr = xr + 64 * S;   // row gradients
@@ -319,7 +311,10 @@ __device__ float wide_tile(const float *__restrict__ X, int n, int d, int I, int
         }
         if (FLUSH && __ballot(!(r2 >= far2)) == 0ull) continue;  // wave-uniform: every pair far
         float dl, cc, w = 0.0f;
-        pair_eval_t<EX == kExZ>(r2, 1.0f, P, dl, cc, w);
+        if (D == 16)
+            nonedge<EX == kExZ>(r2 + kFltMin, P, ltab, table_offset(P, kLtabZero), dl, cc, w);
+        else
+            pair_eval_t<EX == kExZ, !FLUSH>(r2, 1.0f, P, dl, cc, w);  // flushed far pairs need no tail
         if (masked) {
             bool valid = (i < j) && (j < n);
             dl = valid ? dl : 0.0f;
@@ -370,7 +365,7 @@ __global__ __launch_bounds__(64) void k_sweep_wide(const float *__restrict__ X, 
     if (P.reverse) t = items - 1 - t;
     int I, J;
     item_tile(t, nt, shard, nshards, I, J);
-    float l = wide_tile<D, EX, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f);
+    float l = wide_tile<D, EX, false>(X, n, d, I, J, G, rowloss, P, lds, 0.0f, nullptr);
     if (threadIdx.x == 0) partials[t] = l;
 }
 
@@ -383,12 +378,14 @@ __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict_
                                                         float *__restrict__ partials, PairParams P, float far2,
                                                         const unsigned char *__restrict__ dense) {
     extern __shared__ float lds[];
+    __shared__ float4 ltab[D == 16 ? kLtabF4 : 1];
+    if (D == 16) stage_ltab(ltab);  // ordered before use by the tile's first barrier
     const int cnt = *count;
     for (int q = blockIdx.x; q < cnt; q += gridDim.x) {
         if (!dense[q]) continue;  // finished by the sparse pass (k_near_tiles)
         int I, J;
         tile_of(list[q], nt, I, J);
-        float l = wide_tile<D, EX, true>(X, n, d, I, J, G, rowloss, P, lds, far2);
+        float l = wide_tile<D, EX, true>(X, n, d, I, J, G, rowloss, P, lds, far2, ltab);
         if (threadIdx.x == 0) partials[q] = l;
     }
 }
@@ -509,6 +506,13 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
     constexpr int C = D / 16;
     __shared__ float wsum[4];
     __shared__ unsigned whit[4];
+    // d = 16 (the BF16 path) takes the non-edge value from the table, as its near-pair and
+    // dense passes do
+    __shared__ float4 ltab[D == 16 ? kLtabF4 : 1];
+    if (D == 16) {
+        stage_ltab(ltab);
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = lane >> 4, sub = lane & 15;
     const int i = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wave);
@@ -537,7 +541,10 @@ __global__ __launch_bounds__(256) void k_edges_rows(const float *__restrict__ X,
                 const float r2 = group16_sqdist<C>(xr, X + (size_t)(valid ? j : i) * d, sub, d, df);
                 float dlp, ccp, dln, ccn, wp = 0.0f, wn = 0.0f;
                 pair_eval_t<EX == kExZ>(r2, -1.0f, P, dlp, ccp, wp);
-                pair_eval_t<EX == kExZ>(r2, 1.0f, P, dln, ccn, wn);
+                if (D == 16)
+                    nonedge<EX == kExZ>(r2 + kFltMin, P, ltab, table_offset(P, kLtabZero), dln, ccn, wn);
+                else
+                    pair_eval_t<EX == kExZ>(r2, 1.0f, P, dln, ccn, wn);
                 const float dcc = valid ? ccp - ccn : 0.0f;
 #pragma unroll
                 for (int q = 0; q < C; ++q) g[q] = __builtin_fmaf(dcc, df[q], g[q]);
@@ -952,6 +959,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr long long kPersistMaxTiles = 65536;  // 64x64 tiles: n up to ~23k
 constexpr int kMfmaMinN = 8192;                 // d = 16 sweeps on the matrix cores from this n on
+constexpr int kMfmaWideMinN = 4096;             // d = 32, 64, 128 likewise
 constexpr int kEdgesPerUnit = 64;
 constexpr int kRed1Blocks = 1024;  // first level of the FP64 loss reduction  // CSR entries per edge wave: one per lane
 
@@ -1011,10 +1019,11 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
                              : (int)std::max<long long>(1, (g->nnz + kEdgeBlock - 1) / kEdgeBlock);
     p.partials = p.items + p.edge_blocks;
 
-    // d = 16 on the matrix cores for large n (loss and gradient without per-vertex extras):
+    // d = 16 (and 32, 64, 128) on the matrix cores for large n (loss and gradient without
+    // per-vertex extras):
     // the longest chunks of column blocks per item (less staging and flushing per pair; 32
     // measured as fast as 64 or 128 on the 1M-vertex graph) that still give 16,384 items
-    if (d == 16 && g->n >= kMfmaMinN) {
+    if ((d == 16 && g->n >= kMfmaMinN) || ((d == 32 || d == 64 || d == 128) && g->n >= kMfmaWideMinN)) {
         for (int chunk : {32, 16, 8}) {
             const long long it = gempe_mfma_items(g->n, chunk);
             const long long grid = (it + kXcd - 1) / kXcd * kXcd;
@@ -1266,7 +1275,10 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
             launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
     } else if (plan.mfma) {
         TimedLaunches tl(kTkSweep, s);
-        (void)gempe_launch_sweep_mfma16(plan, X, n, grad, partials, pph, s);
+        if (d == 16)
+            (void)gempe_launch_sweep_mfma16(plan, X, n, grad, partials, pph, s);
+        else
+            (void)gempe_launch_sweep_mfma_wide(plan, d, X, n, grad, partials, pph, s);
     } else {
         TimedLaunches tl(kTkSweep, s);
         launch_sweep<EX>(plan, s, X, n, d, grad, extra, partials, P);
@@ -1275,9 +1287,9 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     float *epart = partials + plan.items;
     if (plan.D > 16 || plan.bf16) {
         // wide, and every BF16 plan: one wave per CSR row (also writes the partial of rows
-        // without edges), with the squared distance (group16_sqdist) and the closed-form pair
-        // function of the BF16 path's exact near-pair pass, so a near edge's non-edge term
-        // cancels there bit for bit
+        // without edges), with the squared distance (group16_sqdist) and the non-edge pair
+        // function of the BF16 path's exact near-pair passes (the table at d = 16, the closed
+        // form above), so a near edge's non-edge term cancels there bit for bit
 #define GEMPE_EDGES_ROWS(DD)                                                                              \
     hipLaunchKernelGGL((k_edges_rows<DD, EX>), dim3(plan.edge_blocks), dim3(256), 0, s, X, n, d, g->row_ptr, \
                        g->col_idx, g->hash, (unsigned long long)g->hash_cap, grad, extra, epart, hits, P,    \

@@ -44,7 +44,7 @@
 #include <algorithm>
 
 #include "internal.h"
-#include "ltab.h"
+#include "ltab_stage.h"
 #include "pairfn.h"
 #include "tiles.h"
 
@@ -53,11 +53,14 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMfLtabF4 = GEMPE_LTAB_SEGS + 1;
-constexpr int kMfLtabZero = (int)(-GEMPE_LTAB_LO * GEMPE_LTAB_INV_H);
 constexpr int kMS = 20;                    // LDS stride of a staged column (floats)
 constexpr float kNearKappa = 1.0f / 16.0f;  // Gram pairs need r2 > kappa (|x_i|^2 + |x_j|^2)
 constexpr int kListSlots = 128;             // list slots per workgroup in the BF16 path's dense pass
+// A Gram pair's dl and coefficient come from the staged table (c0 raised by kTabLogScale) as
+// 2^32 times their values, so that far pairs (dl below 2^-126) stay normal; the coefficient
+// block, the row and column sums and the loss are carried times 2^32 and scaled back
+// (exactly) at the flushes.  The exact near pairs return unscaled values.
+constexpr float kCScale = 0x1p32f, kCUnscale = kTabUnscale;
 
 // Position of coordinate k in a staged column: lane (g, c) reads coordinates g, 4+g, 8+g,
 // 12+g of column c as one 16-byte LDS load.
@@ -86,23 +89,47 @@ __device__ inline void mfma_item(long long t, int nb, int nJ, int C, int &I, int
     I = (int)(t - start(lo));
 }
 
-// The exact evaluation of one near pair: the squared distance in difference form from
-// FLT_MIN and the non-edge value of the edge correction (same functions and coordinate order,
-// so an edge among the near pairs cancels bit for bit), its gradient added directly to both
-// ends.  Two passes over the coordinates (the differences recomputed for the gradient) keep
-// only a few values live inside the sweep's register-heavy loop.
+// row16_sum's combination of 16 partial sums (one per lane of a DPP row), in one lane:
+// partial t meets t + 8, then t + 4, then t + 2, then t + 1.  Every add there pairs the same
+// two values in both lanes, so this gives the bits every lane of the row ends with.
+__device__ __forceinline__ float row16_order(const float (&a)[16]) {
+    float b[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) b[t] = a[t] + a[t + 8];
+    const float c0 = b[0] + b[4], c1 = b[1] + b[5], c2 = b[2] + b[6], c3 = b[3] + b[7];
+    return (c0 + c2) + (c1 + c3);
+}
+
+// The exact evaluation of one near pair, its gradient added directly to both ends, with the
+// squared distance and non-edge value of the edge correction that runs beside the sweep, so
+// that an edge among the near pairs cancels bit for bit: G16 = false (the FP32 evaluation,
+// corrected by the COO edge pass) the difference form from FLT_MIN in coordinate order;
+// G16 = true (the BF16 path, corrected by the row-wave pass) group16_sqdist's sum order plus
+// FLT_MIN; the table in both.  Two passes over the coordinates (the differences recomputed
+// for the gradient) keep only a few values live inside the sweep's register-heavy loop.
+template <bool G16>
 __device__ __forceinline__ float near_pair(const float *__restrict__ X, int i, int j, const float *__restrict__ ycolj,
                                            float *__restrict__ G, const PairParams &P, const float4 *ltab,
                                            float tko) {
     const float *xi = X + (size_t)i * 16;
-    float r2 = 1.17549435e-38f;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const float df = xi[k] - ycolj[perm16(k)];
-        r2 = __builtin_fmaf(df, df, r2);
-    }
     float dl, cc, w;
-    nonedge_eval<false, false, true>(r2, P, ltab, tko, GEMPE_LTAB_SEGS, dl, cc, w);
+    if (G16) {
+        float a[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const float df = xi[k] - ycolj[perm16(k)];
+            a[k] = __builtin_fmaf(df, df, 0.0f);
+        }
+        nonedge_eval<false, false, true>(row16_order(a) + kFltMin, P, ltab, tko, GEMPE_LTAB_SEGS, dl, cc, w);
+    } else {
+        float r2 = 1.17549435e-38f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const float df = xi[k] - ycolj[perm16(k)];
+            r2 = __builtin_fmaf(df, df, r2);
+        }
+        nonedge_eval<false, false, true>(r2, P, ltab, tko, GEMPE_LTAB_SEGS, dl, cc, w);
+    }
 #pragma unroll 4
     for (int k = 0; k < 16; ++k) {
         const float v = cc * (xi[k] - ycolj[perm16(k)]);
@@ -233,14 +260,14 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
             const int i = r0 + 4 * g + v;
             const bool valid = !MASK || (j > i && j < n && i < n);
             if (valid && acc[v] <= kNearKappa * (ni[v] + nj))
-                loss += near_pair(X, i, j, ycol + (16 * q + c) * kMS, G, P, ltab, tko);
+                loss += near_pair<FLUSH>(X, i, j, ycol + (16 * q + c) * kMS, G, P, ltab, tko) * kCScale;
         }
     }
 }
 
 // LDS of one matrix-core workgroup.
 struct MfLds {
-    float4 ltab[kMfLtabF4];
+    float4 ltab[kLtabF4];
     __attribute__((aligned(16))) float ycol[64 * kMS];
     float ynrm[64];
     __attribute__((aligned(16))) float tr[4][16 * kMS];
@@ -305,7 +332,7 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
         else
             mfma_block<false, FLUSH>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT,
                                      S, lblk, G, P, L.ltab, tko, far2, g, c);
-        loss += lblk;
+        loss += lblk * kCUnscale;
         __syncthreads();
         // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order
         for (int k = threadIdx.x; k < 64 * 16; k += 256) {
@@ -315,7 +342,8 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
                                  (L.colp[2][col * 17 + kk] + L.colp[3][col * 17 + kk]);
                 const float ts = (L.colp[0][col * 17 + 16] + L.colp[1][col * 17 + 16]) +
                                  (L.colp[2][col * 17 + 16] + L.colp[3][col * 17 + 16]);
-                atomicAdd(&G[(size_t)j * 16 + kk], __builtin_fmaf(ts, L.ycol[col * kMS + perm16(kk)], -cs));
+                atomicAdd(&G[(size_t)j * 16 + kk],
+                          __builtin_fmaf(ts, L.ycol[col * kMS + perm16(kk)], -cs) * kCUnscale);
             }
         }
     }
@@ -333,7 +361,7 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int k = 4 * g + v;
-            atomicAdd(&G[(size_t)i * 16 + k], __builtin_fmaf(si, X[(size_t)i * 16 + k], -RT[v]));
+            atomicAdd(&G[(size_t)i * 16 + k], __builtin_fmaf(si, X[(size_t)i * 16 + k], -RT[v]) * kCUnscale);
         }
     }
     const float ws = wave_sum(loss);
@@ -342,9 +370,6 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
     return (L.lsum[0] + L.lsum[1]) + (L.lsum[2] + L.lsum[3]);
 }
 
-__device__ __forceinline__ void stage_table(MfLds &L) {
-    for (int q = threadIdx.x; q < kMfLtabF4; q += 256) L.ltab[q] = reinterpret_cast<const float4 *>(kLtab)[q];
-}
 
 }  // namespace
 
@@ -355,11 +380,11 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ 
     long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
     if (P.reverse) t = items - 1 - t;
-    stage_table(L);  // the strip's first barrier orders it before any use
+    stage_ltab(L.ltab);  // the strip's first barrier orders it before any use
     int I, J;
     mfma_item(t, nb, nJ, C, I, J);
     const float l = mfma_strip<false>(X, n, I, max(J * C, I), min(J * C + C, nb), G, P,
-                                      table_offset(P, kMfLtabZero), 0.0f, L);
+                                      table_offset(P, kLtabZero), 0.0f, L);
     if (threadIdx.x == 0) partials[t] = l;
 }
 
@@ -374,8 +399,8 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16_list(const float *__restri
                                                            float *__restrict__ G, float *__restrict__ partials,
                                                            PairParams P, float far2) {
     __shared__ MfLds L;
-    stage_table(L);
-    const float tko = table_offset(P, kMfLtabZero);
+    stage_ltab(L.ltab);
+    const float tko = table_offset(P, kLtabZero);
     const int cnt = *count;
     // workgroup w owns slots [S w, S w + S), S = kListSlots (and the same range one grid further on); a
     // run of dense slots holding consecutive tiles of one strip is one strip call (rows loaded
@@ -399,6 +424,276 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16_list(const float *__restri
             q = r;
         }
     }
+}
+
+// ------------------------------------------------------------------------------------
+// The same decomposition for d = 32, 64, 128 (D = 16 M).  Per 16 x 16 block a wave issues
+// D/4 MFMAs for the Gram and D/4 for each gradient side: the coordinates form M chunks of
+// 16, each chunk one 16 x 16 output block of the column-side product (A = x_I in the layout
+// lane (g, c) -> x[i0 + 4g + v][16m + c]) and of the row-side product (A = x_J in the layout
+// lane (g, c) -> x[j0 + 4g + blk][16m + c]).  A staged column keeps its coordinates in
+// chunks of 16, each in the perm16 order, so a lane's Gram operands of a chunk are one
+// 16-byte load.  The four waves' column partials (D x 16 per column group) meet in LDS per
+// column group and leave with one atomic per (column, coordinate) per 64-row strip.
+// ------------------------------------------------------------------------------------
+namespace {
+
+template <int D>
+struct MfLdsW {
+    static constexpr int kS = D + 4;  // column stride (16-byte aligned rows)
+    float4 ltab[kLtabF4];
+    __attribute__((aligned(16))) float ycol[64 * kS];
+    float ynrm[64];
+    __attribute__((aligned(16))) float tr[4][16 * kMS];
+    float colq[4][16 * (D + 1)];
+    float lsum[4];
+};
+
+// The exact evaluation of one near pair at d = 32, 64, 128: the squared distance in
+// difference form from FLT_MIN in coordinate order and the table.  It agrees with the wide
+// edge correction (group16_sqdist and the closed form) to rounding, as the VALU wide sweep
+// does; forming that pass's bits here (16 partial sums in its order, the closed form) costs
+// these register-bound kernels 60 to 70 VGPRs.
+template <int D>
+__device__ __forceinline__ float near_pair_w(const float *__restrict__ X, int i, int j, const float *__restrict__ ycolj,
+                                             float *__restrict__ G, const PairParams &P, const float4 *ltab,
+                                             float tko) {
+    const float *xi = X + (size_t)i * D;
+    float r2 = 1.17549435e-38f;
+#pragma unroll 8
+    for (int k = 0; k < D; ++k) {
+        const float df = xi[k] - ycolj[(k & ~15) + perm16(k & 15)];
+        r2 = __builtin_fmaf(df, df, r2);
+    }
+    float dl, cc, w;
+    nonedge_eval<false, false, true>(r2, P, ltab, tko, GEMPE_LTAB_SEGS, dl, cc, w);
+#pragma unroll 4
+    for (int k = 0; k < D; ++k) {
+        const float v = cc * (xi[k] - ycolj[(k & ~15) + perm16(k & 15)]);
+        atomicAdd(&G[(size_t)i * D + k], v);
+        atomicAdd(&G[(size_t)j * D + k], -v);
+    }
+    return dl;
+}
+
+template <int D, bool MASK>
+__device__ __forceinline__ void mfma_block_w(const float *__restrict__ X, int n, int r0, int j0,
+                                             const float (&GA)[D / 4], const float (&CA)[D / 16][4],
+                                             const float (&ni)[4], float nimax, MfLdsW<D> &L, int wave,
+                                             v4f (&RT)[D / 16], float (&S)[4], float &loss, float *__restrict__ G,
+                                             const PairParams &P, float tko, int g, int c) {
+    constexpr int M = D / 16, kS = MfLdsW<D>::kS;
+    float *tb = L.tr[wave];
+    for (int q = 0; q < 4; ++q) {
+        const float *ycj = L.ycol + (16 * q + c) * kS;
+        const float nj = L.ynrm[16 * q + c];
+        const int j = j0 + 16 * q + c;
+        v4f acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = ni[v] + nj;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float4 gb = *reinterpret_cast<const float4 *>(ycj + 16 * m + 4 * g);
+            acc = mfma(GA[4 * m + 0], gb.x, acc);
+            acc = mfma(GA[4 * m + 1], gb.y, acc);
+            acc = mfma(GA[4 * m + 2], gb.z, acc);
+            acc = mfma(GA[4 * m + 3], gb.w, acc);
+        }
+        float C[4], rinv[4], f[4], dl[4];
+        unsigned off[4];
+        bool valid[4];
+        float mn = 3.0e38f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = r0 + 4 * g + v;
+            valid[v] = !MASK || (j > i && j < n && i < n);
+            const float r2 = acc[v];
+            mn = valid[v] ? fminf(mn, r2) : mn;
+            rinv[v] = hw_rsq(r2);
+            const float delta = r2 * rinv[v];
+            const float tk = __builtin_fmaf(delta, P.tk_scale, tko);
+            f[v] = __builtin_amdgcn_fractf(tk);
+            off[v] = min((unsigned)floor_to_int(tk), (unsigned)GEMPE_LTAB_SEGS) << 4;
+        }
+        float4 cf[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            cf[v] = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(L.ltab) + off[v]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float p = cf[v].w * f[v];
+            const float qq = cf[v].z + p;
+            const float Lv = __builtin_fmaf(__builtin_fmaf(qq, f[v], cf[v].y), f[v], cf[v].x);
+            const float Lf = __builtin_fmaf(__builtin_fmaf(qq, 2.0f, p), f[v], cf[v].y);
+            dl[v] = hw_exp2(Lv);
+            C[v] = dl[v] * (Lf * (P.slope_k * rinv[v]));
+            if (MASK) {
+                dl[v] = valid[v] ? dl[v] : 0.0f;
+                C[v] = valid[v] ? C[v] : 0.0f;
+            }
+        }
+        // near pairs: exact, out of the MFMA products (rare at a spread start)
+        if (__builtin_expect(__ballot(mn <= kNearKappa * (nimax + nj)) != 0ull, 0)) {
+            for (int v = 0; v < 4; ++v) {
+                if (valid[v] && acc[v] <= kNearKappa * (ni[v] + nj)) {
+                    dl[v] = near_pair_w<D>(X, r0 + 4 * g + v, j, ycj, G, P, L.ltab, tko) * kCScale;
+                    C[v] = 0.0f;
+                }
+            }
+        }
+        float T = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            loss += dl[v];
+            S[v] += C[v];
+            T += C[v];
+        }
+        // column side: Col^T[16m + 4g + v][c] of this wave's 16 rows, into its LDS slot
+        float *cq = L.colq[wave];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            v4f CT = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) CT = mfma(CA[m][v], C[v], CT);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cq[c * (D + 1) + 16 * m + 4 * g + v] = CT[v];
+        }
+        T += __shfl_xor(T, 16, 64);
+        T += __shfl_xor(T, 32, 64);
+        if (g == 0) cq[c * (D + 1) + D] = T;
+        // row side: the cc block transposed through LDS, then one 16 x 16 output per chunk
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tb[(4 * g + v) * kMS + c] = C[v];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float4 ct = *reinterpret_cast<const float4 *>(tb + c * kMS + 4 * g);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float *ra = L.ycol + (16 * q + 4 * g) * kS + 16 * m + perm16(c);
+            RT[m] = mfma(ra[0 * kS], ct.x, RT[m]);
+            RT[m] = mfma(ra[1 * kS], ct.y, RT[m]);
+            RT[m] = mfma(ra[2 * kS], ct.z, RT[m]);
+            RT[m] = mfma(ra[3 * kS], ct.w, RT[m]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        // the four waves' partials of these 16 columns, summed in wave order:
+        // g_j += T_j x_j - sum_i cc_ij x_i
+        __syncthreads();
+        for (int k = threadIdx.x; k < 16 * D; k += 256) {
+            const int col = k / D, kk = k - col * D, jj = j0 + 16 * q + col;
+            if (jj < n) {
+                const int o = col * (D + 1);
+                const float cs = (L.colq[0][o + kk] + L.colq[1][o + kk]) + (L.colq[2][o + kk] + L.colq[3][o + kk]);
+                const float ts = (L.colq[0][o + D] + L.colq[1][o + D]) + (L.colq[2][o + D] + L.colq[3][o + D]);
+                const float xj = L.ycol[(16 * q + col) * kS + (kk & ~15) + perm16(kk & 15)];
+                atomicAdd(&G[(size_t)jj * D + kk], __builtin_fmaf(ts, xj, -cs) * kCUnscale);
+            }
+        }
+        __syncthreads();  // the slots are rewritten by the next column group
+    }
+}
+
+template <int D>
+__device__ float mfma_strip_w(const float *__restrict__ X, int n, int I, int b0, int b1, float *__restrict__ G,
+                              const PairParams &P, float tko, MfLdsW<D> &L) {
+    constexpr int M = D / 16, kS = MfLdsW<D>::kS;
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int r0 = I * 64 + wave * 16;
+    float GA[D / 4], CA[M][4], ni[4], S[4];
+#pragma unroll
+    for (int kb = 0; kb < D / 4; ++kb) {
+        const int i = r0 + c;
+        GA[kb] = i < n ? -2.0f * X[(size_t)i * D + 4 * kb + g] : 0.0f;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = r0 + 4 * g + v;
+        float sq = 0.0f;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            CA[m][v] = i < n ? X[(size_t)i * D + 16 * m + c] : 0.0f;
+            sq = __builtin_fmaf(CA[m][v], CA[m][v], sq);
+        }
+        ni[v] = row16_sum(sq);
+        S[v] = 0.0f;
+    }
+    const float nimax = fmaxf(fmaxf(ni[0], ni[1]), fmaxf(ni[2], ni[3]));
+    v4f RT[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) RT[m] = v4f{0.f, 0.f, 0.f, 0.f};
+    float loss = 0.0f;
+    for (int b = b0; b < b1; ++b) {
+        const int j0 = b * 64;
+        float lblk = 0.0f;
+        __syncthreads();  // the previous block's staged columns are consumed
+        // stage 64 columns: float4 f of column col goes to chunk f / 4, perm16 order
+        for (int k = threadIdx.x; k < 64 * (D / 4); k += 256) {
+            const int col = k / (D / 4), f4 = k - col * (D / 4), j = j0 + col;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < n) v = *reinterpret_cast<const float4 *>(X + (size_t)j * D + 4 * f4);
+            float *dst = L.ycol + col * kS + 16 * (f4 >> 2);
+            const int k0 = 4 * (f4 & 3);
+            dst[perm16(k0 + 0)] = v.x;
+            dst[perm16(k0 + 1)] = v.y;
+            dst[perm16(k0 + 2)] = v.z;
+            dst[perm16(k0 + 3)] = v.w;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {  // squared norms of the staged columns
+            const float *yc = L.ycol + threadIdx.x * kS;
+            float sq = 0.0f;
+            for (int k = 0; k < D; ++k) sq = __builtin_fmaf(yc[k], yc[k], sq);
+            L.ynrm[threadIdx.x] = sq;
+        }
+        __syncthreads();
+        const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
+        if (masked)
+            mfma_block_w<D, true>(X, n, r0, j0, GA, CA, ni, nimax, L, wave, RT, S, lblk, G, P, tko, g, c);
+        else
+            mfma_block_w<D, false>(X, n, r0, j0, GA, CA, ni, nimax, L, wave, RT, S, lblk, G, P, tko, g, c);
+        loss += lblk * kCUnscale;
+    }
+    // g_i += S_i x_i - sum_j cc_ij x_j: lane (g, c) holds coordinates 16m + 4g .. + 3 of row r0 + c
+    float Srow[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Srow[v] = row16_sum(S[v]);
+    const int src = (c >> 2) * 16;
+    const float s0 = __shfl(Srow[0], src, 64), s1 = __shfl(Srow[1], src, 64), s2 = __shfl(Srow[2], src, 64),
+                s3 = __shfl(Srow[3], src, 64);
+    const float si = (c & 3) == 0 ? s0 : (c & 3) == 1 ? s1 : (c & 3) == 2 ? s2 : s3;
+    const int i = r0 + c;
+    if (i < n) {
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int k = 16 * m + 4 * g + v;
+                atomicAdd(&G[(size_t)i * D + k], __builtin_fmaf(si, X[(size_t)i * D + k], -RT[m][v]) * kCUnscale);
+            }
+    }
+    const float ws = wave_sum(loss);
+    if (lane == 0) L.lsum[wave] = ws;
+    __syncthreads();
+    return (L.lsum[0] + L.lsum[1]) + (L.lsum[2] + L.lsum[3]);
+}
+
+}  // namespace
+
+template <int D>
+__global__ __launch_bounds__(256) void k_sweep_mfma_wide(const float *__restrict__ X, int n, int nb, int nJ, int C,
+                                                         long long items, long long per_xcd, float *__restrict__ G,
+                                                         float *__restrict__ partials, PairParams P) {
+    __shared__ MfLdsW<D> L;
+    long long t = xcd_item(blockIdx.x, per_xcd);
+    if (t >= items) return;  // uniform over the workgroup
+    if (P.reverse) t = items - 1 - t;
+    stage_ltab(L.ltab);
+    int I, J;
+    mfma_item(t, nb, nJ, C, I, J);
+    const float l = mfma_strip_w<D>(X, n, I, max(J * C, I), min(J * C + C, nb), G, P, table_offset(P, kLtabZero), L);
+    if (threadIdx.x == 0) partials[t] = l;
 }
 
 }  // namespace gempe
@@ -432,5 +727,22 @@ hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, i
         (unsigned)std::max<long long>(1, std::min<long long>((pl.items + kListSlots - 1) / kListSlots, 8192));
     hipLaunchKernelGGL(k_sweep_mfma16_list, dim3(grid), dim3(256), 0, s, X, n, nb, gc.list, gc.count, gc.dense, G,
                        partials, P, gc.theta0 * gc.theta0);
+    return hipGetLastError();
+}
+
+hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
+                                        const PairParamsHost &pph, hipStream_t s) {
+    const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,   pph.tk_off,
+                       pph.slope_k, pph.r_scale,  pph.w_scale, pph.wk2,     pph.table_full, pph.reverse};
+    const int nb = (n + 63) / 64;
+    const int nJ = (nb + pl.mfma_chunk - 1) / pl.mfma_chunk;
+    const long long per = pl.grid / kXcd;
+    const dim3 grid((unsigned)pl.grid), block(256);
+    switch (d) {
+        case 32: hipLaunchKernelGGL(k_sweep_mfma_wide<32>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
+        case 64: hipLaunchKernelGGL(k_sweep_mfma_wide<64>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
+        case 128: hipLaunchKernelGGL(k_sweep_mfma_wide<128>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }

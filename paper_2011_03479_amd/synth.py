@@ -263,6 +263,9 @@ def workload(name: str) -> Workload:
     if name == "sbm100k":  # SBM 50 x 2000, p_in 2e-3, p_out 2e-5, d=128, bf16 Gram, 20 iterations
         g = sbm(50, 2000, 2e-3, 2e-5, seed=3)
         return Workload(name, g, 128, init_embedding(g.n, 128, 1003), 20, step_size(g.n), "bf16")
+    if name == "sbm100k_fp32":  # the SBM workload with every pair in FP32 (the other side of FP32 vs BF16)
+        g = sbm(50, 2000, 2e-3, 2e-5, seed=3)
+        return Workload(name, g, 128, init_embedding(g.n, 128, 1003), 20, step_size(g.n), "fp32")
     if name == "sbm100k_t9":  # the same graph from a contracted start: X0 ~ N(0, (mu / sqrt(2d))^2),
         # so that the typical distance is about mu and nearly every pair is near
         g = sbm(50, 2000, 2e-3, 2e-5, seed=3)

@@ -124,13 +124,14 @@ def test_bf16_tall_strips_clusters(n, d):
 
 
 def test_bf16_d16_near_edges_cancel():
-    """BF16 at d = 16: a 16-vertex clique packed into a ball of radius 0.03 (every pair a
-    near edge, dl+ ~ 0.1 bit, dl- ~ 3.9 bits) plus far vertices.  The near-pair pass adds
-    each edge's non-edge term and the edge pass subtracts it; computed with the same squared
-    distance and pair function they cancel bit for bit, leaving only the FP32 rounding of
-    dl+ - dl- (~2e-7 relative of 3.9 bits per pair), well inside 5e-6 of the loss.  A
-    non-edge term from another pair function (the table's ~1e-6 relative error) would move
-    the loss by ~2e-5."""
+    """BF16 at d = 16: a 16-vertex clique packed into a ball of radius 0.03 at the origin
+    (every pair an edge close in tau, dl+ ~ 0.1 bit, dl- ~ 3.9 bits) plus far vertices.  A
+    pass of the sweep adds each edge's non-edge term and the edge pass subtracts it; with the
+    same pair function (the table at d = 16) they agree to the rounding of the squared
+    distance (bit for bit for the exact near pairs), leaving the FP32 rounding of dl+ - dl-
+    (~2e-7 relative of 3.9 bits per pair), well inside 5e-6 of the loss.  A non-edge term
+    from the other pair function (the table's fit error, up to 5e-6 relative) moved the loss
+    by 4.4e-4."""
     n = 300
     rng = np.random.default_rng(41)
     X = rng.standard_normal((n, 16)) * 3.0

@@ -131,3 +131,48 @@ def test_mfma16_cl1m_sampled_rows():
     G = gempe.Graph(g.n, g.row_ptr, g.col_idx)
     check_rows_plain(g, G, w.X0, rows, what="mfma16 cl1m")
     G.close()
+
+
+@pytest.mark.parametrize("n,d", [(4100, 32), (4500, 64), (4160, 128)])
+def test_mfma_wide_whole_graph(n, d):
+    """d = 32, 64, 128 on the matrix cores (n >= 4096): whole-graph parity, ragged n."""
+    g = synth.chung_lu(n, 10.0, 2.4, seed=n + d)
+    X = synth.init_embedding(n, d, seed=3 * n + d)
+    note(f"mfma wide whole graph n={n} d={d} m={g.m}")
+    _full(g, X, f"mfma wide n{n} d{d}")
+
+
+@pytest.mark.parametrize("d", [32, 128])
+def test_mfma_wide_near_pairs(d):
+    """Clusters away from the origin (near pairs on the exact path) and, at d = 32, a
+    translated embedding (every pair near)."""
+    from test_gpu_bf16 import clusters
+
+    n = 4200
+    X, lab = clusters(n, d, 30, spread=0.1, sep=3.0, seed=d)
+    rng = np.random.default_rng(d)
+    u = rng.integers(0, n, 3 * n)
+    members = [np.nonzero(lab == k)[0] for k in range(30)]
+    same = np.array([rng.choice(members[lab[a]]) for a in u[:2 * n]])
+    g = synth.csr_from_edges(n, u, np.concatenate([same, rng.integers(0, n, n)]))
+    note(f"mfma wide clusters d={d}")
+    _full(g, X, f"mfma wide clusters d{d}")
+    if d == 32:
+        Xt = (synth.init_embedding(n, d, seed=5).astype(np.float64) + 30.0).astype(np.float32)
+        note("mfma wide translated d=32")
+        _full(g, Xt, "mfma wide translated d32")
+
+
+def test_mfma_wide_reversed_tile_order():
+    n, d = 4400, 64
+    g = synth.chung_lu(n, 10.0, 2.5, seed=23)
+    X = synth.init_embedding(n, d, seed=24)
+    note("mfma wide reversed tile order")
+    require_gpu()
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    fwd = _plain(G, X)
+    rev = _plain(G, X, params=gempe.params_default(flags=gempe.GEMPE_F_REVERSE_TILES))
+    assert rev[0] == fwd[0], (rev[0], fwd[0])
+    A = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_abs_slope=True)["abs_slope"]
+    assert_grad_close(rev[1], fwd[1], A, rtol=1e-5, what="mfma wide reversed")
+    G.close()
