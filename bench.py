@@ -62,7 +62,7 @@ def measured_traffic(kernel: str, workload: str):
 
 
 TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/csrc/sweep_mfma.hip",
-                   "paper_2011_03479_amd/csrc/pairfn.h",
+                   "paper_2011_03479_amd/csrc/pairfn.h", "paper_2011_03479_amd/csrc/ltab_stage.h",
                    "paper_2011_03479_amd/csrc/ltab.h", "paper_2011_03479_amd/csrc/erfcx_coef.h",
                    "paper_2011_03479_amd/csrc/millsq_coef.h", "paper_2011_03479_amd/csrc/tiles.h",
                    "paper_2011_03479_amd/csrc/internal.h"]
@@ -343,11 +343,30 @@ def attach_traffic(roof, kernel: str, workload: str):
         "source": f"profiles/traffic_{workload}.json (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)"}
 
 
+def traffic_kernel_of(w):
+    """The symbol of the FP32 workload's dominant kernel, as rocprofv3 names it (the key of its
+    traffic record), or None."""
+    if w.precision != "fp32":
+        return None
+    d, n = w.d, w.graph.n
+    if n <= 23000 and d <= 16:
+        return f"gempe::k_iter<{d if d <= 4 else (8 if d <= 8 else 16)}>"
+    if d == 16 and n >= 8192:
+        return "gempe::k_sweep_mfma16"
+    if d in (32, 64, 128) and n >= 4096:
+        return f"gempe::k_sweep_mfma_wide<{d}>"
+    return None
+
+
 def summary(w, r, steps: int, warmup: int):
+    roof = roofline_of(w, r, steps)
+    kern = traffic_kernel_of(w)
+    if kern is not None:
+        attach_traffic(roof, kern, w.name)
     d = {"workload": w.name, "n": w.graph.n, "m": w.graph.m, "d": w.d, "precision": w.precision,
          "steps": steps, "warmup": warmup, "pairs_per_iter": r["N"], "value": r["value"], "unit": "pairs/s",
          "ms_per_step": r["ms"] / steps, "kernels": r["kernels"], "final_loss_bits": r["final_loss_bits"],
-         "roofline": roofline_of(w, r, steps)}
+         "roofline": roof}
     return d
 
 
@@ -440,8 +459,6 @@ def main():
     r = gd_run(w, steps, args.warmup)
     main_sum = summary(w, r, steps, args.warmup)
     roof = main_sum["roofline"]
-    if w.precision == "fp32" and w.d <= 16 and w.graph.n > 23000:
-        attach_traffic(roof, args.traffic_kernel, w.name)
     result = {
         "metric": "vertex-pairs/s per full-gradient iteration (FP32; BF16-MFMA Gram variant under variants)",
         "value": r["value"],
