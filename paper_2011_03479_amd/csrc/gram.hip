@@ -435,7 +435,8 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                                                     const int *__restrict__ count, gempe::PairParams P,
                                                     float *__restrict__ G, float *__restrict__ extra,
                                                     float *__restrict__ partials,
-                                                    unsigned char *__restrict__ dense, int all_dense_ok) {
+                                                    unsigned char *__restrict__ dense, int all_dense,
+                                                    int *__restrict__ all_dense_flag) {
     __shared__ int near[4][kSparseNear];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -444,11 +445,17 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
     // when the dense pass can take any flagged tile (all_dense_ok) and most tiles are flagged
     // (d = 16 from a spread start: nearly every pair lies within the near distance), every
     // flagged tile goes to it directly instead of being recomputed here only to be found dense
-    if (all_dense_ok && 2LL * cnt > nb64 * (nb64 + 1) / 2) {
-        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (long long)gridDim.x * 256)
-            dense[q] = 1;
+    if (all_dense && 2LL * cnt > nb64 * (nb64 + 1) / 2) {
+        for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (long long)gridDim.x * 256) {
+            if (all_dense == 1)
+                dense[q] = 1;
+            else
+                partials[q] = 0.0f;  // the full sweep writes its own slots below cnt
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) *all_dense_flag = all_dense == 2 ? 1 : 0;
         return;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *all_dense_flag = 0;
     // d = 16 takes the non-edge value from the table, as the dense pass and the edge pass do
     __shared__ float4 ltab[D == 16 ? gempe::kLtabF4 : 1];
     if (D == 16) {
@@ -625,13 +632,13 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
 namespace {
 template <int EX>
 void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc, const gempe::PairParams &P,
-                          float *G, float *extra, float *partials, hipStream_t s, int all_dense_ok) {
+                          float *G, float *extra, float *partials, hipStream_t s, int all_dense) {
     const long long nb64 = (g->n + 63) / 64;
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(gc.xb);
     const dim3 grid(kNearTileGrid), block(256);
 #define GEMPE_NEAR(DD)                                                                                     \
     hipLaunchKernelGGL((k_near_tiles<DD, EX>), grid, block, 0, s, xb, X, gc.nrm, gc.smax128, g->n, nb64,  \
-                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense, all_dense_ok)
+                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense, all_dense, gc.all_dense)
     switch (d) {
         case 16: GEMPE_NEAR(16); break;
         case 32: GEMPE_NEAR(32); break;
@@ -648,14 +655,14 @@ void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const G
 
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &h, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s, bool all_dense_ok) {
+                                   hipStream_t s, int all_dense) {
     const gempe::PairParams P{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
                               h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full, 0};
     if (ex == 2)
-        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
+        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s, all_dense);
     else if (ex == 1)
-        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
+        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s, all_dense);
     else
-        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s, all_dense_ok ? 1 : 0);
+        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s, all_dense);
     return hipGetLastError();
 }

@@ -138,7 +138,9 @@ struct SweepPlan {
     int shard = 0, nshards = 1;
     // d = 16, 32, 64, 128 on the matrix cores (loss and gradient only): 64-row strips
     // against chunks of mfma_chunk column blocks of 64; the partial region holds
-    // max(items, mfma_items) slots before the edge blocks' partials
+    // max(items, mfma_items) slots before the edge blocks' partials.  A BF16 plan at d = 16
+    // keeps mfma false and fills the mfma_* fields for its all-dense evaluations (then
+    // 2 mfma_items <= items, so the sweep's slots lie inside the list's cleared ones).
     bool mfma = false;
     int mfma_chunk = 8;
     long long mfma_items = 0, mfma_grid = 0;
@@ -195,6 +197,7 @@ struct GramCtx {
     float theta0 = 0.0f;  // mu + near_k sigma
     unsigned char *dense = nullptr;
     int *chunks = nullptr;
+    int *all_dense = nullptr;  // set by the sparse pass when the full d = 16 sweep takes every tile
 };
 GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p);
 
@@ -206,8 +209,9 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
 // The d = 16 matrix-core sweep (sweep_mfma.hip): items of a plan with mfma_chunk, and the
 // launch over pl.items items with pl.grid workgroups.
 long long gempe_mfma_items(int n, int chunk);
+// gate: the BF16 path's all-dense evaluation (runs only when *gate is set), else null.
 hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
-                                     const PairParamsHost &pph, hipStream_t s);
+                                     const PairParamsHost &pph, hipStream_t s, const int *gate = nullptr);
 // The same for d = 32, 64, 128 (k_sweep_mfma_wide<d>).
 hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
                                         const PairParamsHost &pph, hipStream_t s);
@@ -218,11 +222,13 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
                                     float theta0, int *chunk, hipStream_t s);
 // Sparse exact pass over the flagged tiles (gram.hip); ex: 0 none, 1 row loss, 2 WM z.
-// all_dense_ok: the dense pass can take any flagged tile; when more than half of the tiles
-// are flagged, all of them are then marked dense without being recomputed here.
+// all_dense, when more than half of the tiles are flagged: 0 nothing special; 1 every
+// flagged tile is marked dense for the dense pass without being recomputed here; 2 the full
+// d = 16 matrix-core sweep takes every pair (the list's loss slots are cleared and
+// *gc.all_dense is set, which the dense pass reads and skips).  *gc.all_dense is 0 otherwise.
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &pp, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s, bool all_dense_ok = false);
+                                   hipStream_t s, int all_dense = 0);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s);
 // Continuous batching of fused iterations (sweep.hip): one table row per job.

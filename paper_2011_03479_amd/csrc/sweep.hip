@@ -986,6 +986,20 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
         p.grid = std::min<long long>(p.items, 2048);
         p.edge_blocks = (int)std::max<long long>(1, ((long long)g->n + 3) / 4);  // one wave per row
         p.partials = p.items + p.edge_blocks;
+        // d = 16: an evaluation whose screen flags most tiles (a spread start: nearly every
+        // pair within the near distance) runs the full matrix-core sweep instead of the list
+        if (d == 16 && g->n >= kMfmaMinN) {
+            for (int chunk : {32, 16, 8}) {
+                const long long it = gempe_mfma_items(g->n, chunk);
+                const long long grid = (it + kXcd - 1) / kXcd * kXcd;
+                if ((it >= 16384 || chunk == 8) && grid * 256 < (1LL << 32) && 2 * it <= p.items) {
+                    p.mfma_chunk = chunk;
+                    p.mfma_items = it;
+                    p.mfma_grid = grid;
+                    break;
+                }
+            }
+        }
         return p;
     }
     p.D = padded_dim(d);
@@ -1136,6 +1150,7 @@ GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params 
     c.count = reinterpret_cast<int *>(ws + L.counters + 32);
     c.dense = ws + L.dense;
     c.chunks = reinterpret_cast<int *>(ws + L.chunks);
+    c.all_dense = reinterpret_cast<int *>(ws + L.counters + 36);
     c.theta0 = (float)(p->mu + p->near_k * p->sigma);
     return c;
 }
@@ -1263,16 +1278,26 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     const int n = g->n;
     if (plan.bf16) {
         // near pairs of sparsely flagged tiles exactly, the dense tiles by the LDS tile pass
-        TimedLaunches tl(kTkExact, s, 2);
         // at d = 16 the dense tiles of a plain evaluation go to the matrix cores (FP32 Gram
-        // with the exact path for near pairs); otherwise, and for per-vertex extras, the LDS
-        // tile pass
+        // with the exact path for near pairs), and when most tiles are flagged the full
+        // matrix-core sweep takes every pair (chunk-major, three waves per SIMD; the list
+        // kernel runs at two) while the list kernel exits; otherwise, and for per-vertex
+        // extras, the LDS tile pass
         const bool mf16 = EX == kExNone && d == 16 && pph.table_full;
-        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, mf16);
-        if (mf16)
+        const bool full = mf16 && plan.mfma_items > 0;
+        TimedLaunches tl(kTkExact, s, full ? 3 : 2);
+        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, !mf16 ? 0 : full ? 2 : 1);
+        if (mf16) {
+            if (full) {
+                SweepPlan pm = plan;
+                pm.items = plan.mfma_items;
+                pm.grid = plan.mfma_grid;
+                (void)gempe_launch_sweep_mfma16(pm, X, n, grad, partials, pph, s, gc.all_dense);
+            }
             (void)gempe_launch_sweep_mfma16_list(plan, X, n, gc, grad, partials, pph, s);
-        else
+        } else {
             launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
+        }
     } else if (plan.mfma) {
         TimedLaunches tl(kTkSweep, s);
         if (d == 16)

@@ -142,7 +142,7 @@ __device__ __forceinline__ float near_pair(const float *__restrict__ X, int i, i
 // One 64-column block against the wave's 16 rows.  MASK: the diagonal block or a tail (only
 // pairs i < j < n, i < n count).  FLUSH: pairs with r2 >= far2 add exactly 0 (the BF16 path's
 // far non-edges, flushed as its screen flushes them).
-template <bool MASK, bool FLUSH>
+template <bool MASK, bool FLUSH, bool G16>
 __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, int r0, int j0, const float (&GA)[4],
                                            const float (&CA)[4], const float (&ni)[4], float nimax,
                                            const float *__restrict__ ycol, const float *__restrict__ ynrm,
@@ -260,7 +260,7 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
             const int i = r0 + 4 * g + v;
             const bool valid = !MASK || (j > i && j < n && i < n);
             if (valid && acc[v] <= kNearKappa * (ni[v] + nj))
-                loss += near_pair<FLUSH>(X, i, j, ycol + (16 * q + c) * kMS, G, P, ltab, tko) * kCScale;
+                loss += near_pair<G16>(X, i, j, ycol + (16 * q + c) * kMS, G, P, ltab, tko) * kCScale;
         }
     }
 }
@@ -278,7 +278,7 @@ struct MfLds {
 // Strip I (64 rows, four waves of 16) against column blocks [b0, b1): stage each block, the
 // three products per 16 x 16 block, the column partials per block, the row partials at the
 // end.  Returns the workgroup's FP32 loss in thread 0.
-template <bool FLUSH>
+template <bool FLUSH, bool G16>
 __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, int b1, float *__restrict__ G,
                             const PairParams &P, float tko, float far2, MfLds &L) {
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
@@ -327,10 +327,10 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
         __syncthreads();
         const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
         if (masked)
-            mfma_block<true, FLUSH>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT, S,
+            mfma_block<true, FLUSH, G16>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT, S,
                                     lblk, G, P, L.ltab, tko, far2, g, c);
         else
-            mfma_block<false, FLUSH>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT,
+            mfma_block<false, FLUSH, G16>(X, n, r0, j0, GA, CA, ni, nimax, L.ycol, L.ynrm, L.tr[wave], L.colp[wave], RT,
                                      S, lblk, G, P, L.ltab, tko, far2, g, c);
         loss += lblk * kCUnscale;
         __syncthreads();
@@ -373,18 +373,23 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
 
 }  // namespace
 
+// BF: the BF16 path's evaluation whose screen flagged most tiles; it runs only when the
+// sparse pass set *gate (every pair exact in FP32, near pairs in that path's form).
+template <bool BF>
 __global__ __launch_bounds__(256) void k_sweep_mfma16(const float *__restrict__ X, int n, int nb, int nJ, int C,
                                                       long long items, long long per_xcd, float *__restrict__ G,
-                                                      float *__restrict__ partials, PairParams P) {
+                                                      float *__restrict__ partials, PairParams P,
+                                                      const int *__restrict__ gate) {
     __shared__ MfLds L;
+    if (BF && *gate == 0) return;  // uniform over the grid
     long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
     if (P.reverse) t = items - 1 - t;
     stage_ltab(L.ltab);  // the strip's first barrier orders it before any use
     int I, J;
     mfma_item(t, nb, nJ, C, I, J);
-    const float l = mfma_strip<false>(X, n, I, max(J * C, I), min(J * C + C, nb), G, P,
-                                      table_offset(P, kLtabZero), 0.0f, L);
+    const float l = mfma_strip<false, BF>(X, n, I, max(J * C, I), min(J * C + C, nb), G, P,
+                                          table_offset(P, kLtabZero), 0.0f, L);
     if (threadIdx.x == 0) partials[t] = l;
 }
 
@@ -397,8 +402,9 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16_list(const float *__restri
                                                            const int *__restrict__ count,
                                                            const unsigned char *__restrict__ dense,
                                                            float *__restrict__ G, float *__restrict__ partials,
-                                                           PairParams P, float far2) {
+                                                           PairParams P, float far2, const int *__restrict__ all_dense) {
     __shared__ MfLds L;
+    if (*all_dense) return;  // the full sweep took every tile (uniform over the grid)
     stage_ltab(L.ltab);
     const float tko = table_offset(P, kLtabZero);
     const int cnt = *count;
@@ -416,7 +422,7 @@ __global__ __launch_bounds__(256) void k_sweep_mfma16_list(const float *__restri
             tile_of(list[q], nb, I, J);
             int r = q + 1;
             while (r < end && dense[r] && list[r] == list[r - 1] + 1 && J + (r - q) < nb) ++r;
-            const float l = mfma_strip<true>(X, n, I, J, J + (r - q), G, P, tko, far2, L);
+            const float l = mfma_strip<true, true>(X, n, I, J, J + (r - q), G, P, tko, far2, L);
             if (threadIdx.x == 0) {
                 partials[q] = l;
                 for (int z = q + 1; z < r; ++z) partials[z] = 0.0f;
@@ -707,14 +713,18 @@ long long gempe_mfma_items(int n, int chunk) {
 }
 
 hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
-                                     const PairParamsHost &pph, hipStream_t s) {
+                                     const PairParamsHost &pph, hipStream_t s, const int *gate) {
     const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,   pph.tk_off,
                        pph.slope_k, pph.r_scale,  pph.w_scale, pph.wk2,     pph.table_full, pph.reverse};
     const int nb = (n + 63) / 64;
     const int nJ = (nb + pl.mfma_chunk - 1) / pl.mfma_chunk;
     const long long per = pl.grid / kXcd;
-    hipLaunchKernelGGL(k_sweep_mfma16, dim3((unsigned)pl.grid), dim3(256), 0, s, X, n, nb, nJ, pl.mfma_chunk,
-                       pl.items, per, G, partials, P);
+    if (gate)
+        hipLaunchKernelGGL(k_sweep_mfma16<true>, dim3((unsigned)pl.grid), dim3(256), 0, s, X, n, nb, nJ,
+                           pl.mfma_chunk, pl.items, per, G, partials, P, gate);
+    else
+        hipLaunchKernelGGL(k_sweep_mfma16<false>, dim3((unsigned)pl.grid), dim3(256), 0, s, X, n, nb, nJ,
+                           pl.mfma_chunk, pl.items, per, G, partials, P, gate);
     return hipGetLastError();
 }
 
@@ -726,7 +736,7 @@ hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, i
     const unsigned grid =
         (unsigned)std::max<long long>(1, std::min<long long>((pl.items + kListSlots - 1) / kListSlots, 8192));
     hipLaunchKernelGGL(k_sweep_mfma16_list, dim3(grid), dim3(256), 0, s, X, n, nb, gc.list, gc.count, gc.dense, G,
-                       partials, P, gc.theta0 * gc.theta0);
+                       partials, P, gc.theta0 * gc.theta0, gc.all_dense);
     return hipGetLastError();
 }
 
