@@ -150,20 +150,37 @@ __device__ __forceinline__ void mfma_block(const float *__restrict__ X, int n, i
                                            float &loss, float *__restrict__ G, const PairParams &P,
                                            const float4 *ltab, float tko, float far2, int g, int c) {
     unsigned nearq = 0;  // column groups with near pairs (wave-uniform)
+    // the Gram block of the next column group is issued before this group's pair function,
+    // so the matrix core works on it while the vector ALUs evaluate
+    v4f accn;
+    {
+        const float4 gb = *reinterpret_cast<const float4 *>(ycol + c * kMS + 4 * g);
+        const float nj0 = ynrm[c];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accn[v] = ni[v] + nj0;
+        accn = mfma(GA[0], gb.x, accn);
+        accn = mfma(GA[1], gb.y, accn);
+        accn = mfma(GA[2], gb.z, accn);
+        accn = mfma(GA[3], gb.w, accn);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float4 gb = *reinterpret_cast<const float4 *>(ycol + (16 * q + c) * kMS + 4 * g);
-        const float GB[4] = {gb.x, gb.y, gb.z, gb.w};
+        const v4f acc = accn;
+        if (q < 3) {
+            const float4 gb = *reinterpret_cast<const float4 *>(ycol + (16 * (q + 1) + c) * kMS + 4 * g);
+            const float nj1 = ynrm[16 * (q + 1) + c];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) accn[v] = ni[v] + nj1;
+            accn = mfma(GA[0], gb.x, accn);
+            accn = mfma(GA[1], gb.y, accn);
+            accn = mfma(GA[2], gb.z, accn);
+            accn = mfma(GA[3], gb.w, accn);
+        }
         float RA[4];
 #pragma unroll
         for (int blk = 0; blk < 4; ++blk) RA[blk] = ycol[(16 * q + 4 * g + blk) * kMS + perm16(c)];
         const float nj = ynrm[16 * q + c];
         const int j = j0 + 16 * q + c;
-        v4f acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = ni[v] + nj;
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) acc = mfma(GA[kb], GB[kb], acc);
         // pair function from the table (every non-edge tau of a Gram pair lies in it)
         float C[4], rinv[4], f[4], dl[4];
         unsigned off[4];
@@ -490,21 +507,34 @@ __device__ __forceinline__ void mfma_block_w(const float *__restrict__ X, int n,
                                              const PairParams &P, float tko, int g, int c) {
     constexpr int M = D / 16, kS = MfLdsW<D>::kS;
     float *tb = L.tr[wave];
+    // the Gram block of the next column group is issued before this group's pair function, so
+    // that the matrix core works while the vector ALUs evaluate (not at d = 64: the held block
+    // would cost that kernel its third wave per SIMD)
+    constexpr bool kAhead = D != 64;
+    auto gram = [&](int qq) {
+        const float *ycq = L.ycol + (16 * qq + c) * kS;
+        const float njq = L.ynrm[16 * qq + c];
+        v4f a;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[v] = ni[v] + njq;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const float4 gb = *reinterpret_cast<const float4 *>(ycq + 16 * m + 4 * g);
+            a = mfma(GA[4 * m + 0], gb.x, a);
+            a = mfma(GA[4 * m + 1], gb.y, a);
+            a = mfma(GA[4 * m + 2], gb.z, a);
+            a = mfma(GA[4 * m + 3], gb.w, a);
+        }
+        return a;
+    };
+    v4f accn;
+    if (kAhead) accn = gram(0);
     for (int q = 0; q < 4; ++q) {
         const float *ycj = L.ycol + (16 * q + c) * kS;
         const float nj = L.ynrm[16 * q + c];
         const int j = j0 + 16 * q + c;
-        v4f acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = ni[v] + nj;
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const float4 gb = *reinterpret_cast<const float4 *>(ycj + 16 * m + 4 * g);
-            acc = mfma(GA[4 * m + 0], gb.x, acc);
-            acc = mfma(GA[4 * m + 1], gb.y, acc);
-            acc = mfma(GA[4 * m + 2], gb.z, acc);
-            acc = mfma(GA[4 * m + 3], gb.w, acc);
-        }
+        const v4f acc = kAhead ? accn : gram(q);
+        if (kAhead && q < 3) accn = gram(q + 1);
         float C[4], rinv[4], f[4], dl[4];
         unsigned off[4];
         bool valid[4];
