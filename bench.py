@@ -352,7 +352,7 @@ def traffic_kernel_of(w):
     if n <= 23000 and d <= 16:
         return f"gempe::k_iter<{d if d <= 4 else (8 if d <= 8 else 16)}>"
     if d == 16 and n >= 8192:
-        return "gempe::k_sweep_mfma16"
+        return "gempe::k_sweep_mfma16<false>"
     if d in (32, 64, 128) and n >= 4096:
         return f"gempe::k_sweep_mfma_wide<{d}>"
     return None
@@ -421,7 +421,7 @@ def main():
     ap.add_argument("--record-traffic", default=None, metavar="DIR",
                     help="only write profiles/traffic_<workload>.json from the rocprofv3 --pmc runs under "
                          "DIR (no GPU needed); --traffic-kernel names the kernel")
-    ap.add_argument("--traffic-kernel", default="gempe::k_sweep_mfma16")
+    ap.add_argument("--traffic-kernel", default="gempe::k_sweep_mfma16<false>")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)

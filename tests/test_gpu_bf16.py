@@ -158,3 +158,44 @@ def test_bf16_d16_near_edges_cancel():
                       atol=(n - 1) * BF16_FLUSH_GRAD)
     # the clique's vertices, whose pairs are all near edges, meet the FP32 bound
     assert_grad_close(got["grad"][:16], ref["grad"][:16], ref["abs_slope"][:16], what="bf16 d16 clique vertices")
+
+
+@pytest.mark.parametrize("n,kind", [(9000, "spread"), (8300, "clusters")])
+def test_bf16_d16_full_sweep_route(n, kind):
+    """BF16 at d = 16 from n = 8,192 on.  X ~ N(0, 1): more than half of the tiles are flagged,
+    so the sparse pass hands the evaluation to the full matrix-core sweep (every pair exact in
+    FP32; the dense list kernel exits).  Tight far-apart clusters: most tiles unflagged, the
+    list route.  Both against the whole-graph oracle; the exact pass's launch count shows the
+    route was planned (three launches: sparse pass, full sweep, list)."""
+    if kind == "spread":
+        g = synth.chung_lu(n, 10.0, 2.4, seed=n)
+        X = synth.init_embedding(n, 16, seed=n + 1)
+    else:
+        X, lab = clusters(n, 16, 40, spread=0.1, sep=4.0, seed=n)
+        order = np.argsort(lab, kind="stable")  # vertices by cluster: far tiles off the diagonal
+        X, lab = X[order], lab[order]
+        rng = np.random.default_rng(n)
+        u = rng.integers(0, n, 3 * n)
+        members = [np.nonzero(lab == k)[0] for k in range(40)]
+        same = np.array([rng.choice(members[lab[a]]) for a in u])
+        g = synth.csr_from_edges(n, u, same)
+    note(f"bf16 d16 full-sweep route n={n} {kind} m={g.m}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    gempe.timing_enable(True)
+    gempe.timing_read(gempe.GEMPE_TK_EXACT)
+    got = gpu_loss_grad(G, X, params=gempe.params_default(**BF16))
+    nl, _ = gempe.timing_read(gempe.GEMPE_TK_EXACT)
+    gempe.timing_enable(False)
+    assert nl == 3, nl
+    ref = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_abs_slope=True)
+    assert got["edge_hits"] == g.m == ref["edge_hits"]
+    what = f"bf16 d16 route n{n} {kind}"
+    if kind == "spread":
+        # every pair exact in FP32: the FP32 bounds hold
+        assert abs(got["loss"] - ref["loss"]) <= 1e-5 * ref["loss"], (what, got["loss"], ref["loss"])
+        assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], what=what)
+    else:
+        assert abs(got["loss"] - ref["loss"]) <= BF16_LOSS_RTOL * ref["loss"], (what, got["loss"], ref["loss"])
+        assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], rtol=BF16_GRAD_RTOL, what=what,
+                          atol=(n - 1) * BF16_FLUSH_GRAD)
+    G.close()
