@@ -1277,12 +1277,12 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
                  hipStream_t s, const GramCtx &gc) {
     const int n = g->n;
     if (plan.bf16) {
-        // near pairs of sparsely flagged tiles exactly, the dense tiles by the LDS tile pass
-        // at d = 16 the dense tiles of a plain evaluation go to the matrix cores (FP32 Gram
-        // with the exact path for near pairs), and when most tiles are flagged the full
-        // matrix-core sweep takes every pair (chunk-major, three waves per SIMD; the list
-        // kernel runs at two) while the list kernel exits; otherwise, and for per-vertex
-        // extras, the LDS tile pass
+        // The sparse pass evaluates the near pairs of sparsely flagged tiles exactly and marks
+        // the dense ones.  At d = 16 the dense tiles of a plain evaluation go to the matrix
+        // cores (FP32 Gram, the exact path for near pairs); from n = 8,192 on, when most
+        // tiles are flagged, the full matrix-core sweep takes every pair instead (chunk-major,
+        // four waves per SIMD against the list kernel's three) and the list kernel exits on
+        // the sparse pass's flag.  Otherwise, and for per-vertex extras, the LDS tile pass.
         const bool mf16 = EX == kExNone && d == 16 && pph.table_full;
         const bool full = mf16 && plan.mfma_items > 0;
         TimedLaunches tl(kTkExact, s, full ? 3 : 2);
