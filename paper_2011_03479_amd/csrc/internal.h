@@ -151,7 +151,8 @@ struct SweepPlan {
 long long gempe_shard_items(int nt, int s, int G);
 
 struct WsLayout {
-    size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, ...
+    size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, [16] FP64 loss
+                          // scratch, [32] int flagged-tile count, [36] int all-dense flag (BF16)
     size_t partials = 0;  // float[plan.partials]
     size_t gbuf = 0;      // float[n*d] gradient scratch for gempe_step/gempe_embed
     size_t zbuf = 0;      // float[n] weighted-majorization denominators z_i

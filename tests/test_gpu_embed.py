@@ -22,6 +22,8 @@ def _gpu():
 CASES = [
     (100, 2, 1, True), (100, 2, 1, False), (257, 3, 2, True), (257, 3, 3, False), (1000, 16, 4, True),
     (650, 8, 5, False), (130, 1, 6, True), (70, 2, 0, True), (3400, 2, 7, True), (2000, 5, 2, False),
+    # longer runs: the gradient ring (three slots) and the iterate ping-pong through many cycles
+    (1000, 2, 40, True), (1500, 8, 13, True), (700, 16, 25, False),
 ]
 
 
