@@ -443,8 +443,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "launches": 20}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 (the sweep's "
+                                   "sharding over several GPUs, gempe_loss_grad_shard, is measured per "
+                                   "device, not as a multi-GPU run)"}))
         sys.exit(2)
 
     import torch

@@ -51,7 +51,7 @@ typedef enum gempe_status {
     GEMPE_ERR_NOMEM = -3,        /* workspace too small, or a set-up allocation failed     */
     GEMPE_ERR_HIP = -4,          /* a HIP runtime call failed                              */
     GEMPE_ERR_NUMERIC = -5,      /* non-finite loss or coordinates detected on the device  */
-    GEMPE_ERR_UNSUPPORTED = -6,  /* valid request this build does not implement            */
+    GEMPE_ERR_UNSUPPORTED = -6,  /* valid request the library does not implement           */
     GEMPE_ERR_TIMEOUT = -7       /* a wait exceeded its time limit (serving)               */
 } gempe_status;
 
