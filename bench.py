@@ -356,7 +356,7 @@ def traffic_kernel_of(w):
     if d == 16 and n >= 8192:
         return "gempe::k_sweep_mfma16<false>"
     if d in (32, 64, 128) and n >= 4096:
-        return f"gempe::k_sweep_mfma_wide<{d}>"
+        return f"gempe::k_sweep_mfma_wide<{d}, false>"
     return None
 
 

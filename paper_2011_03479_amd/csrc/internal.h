@@ -215,7 +215,7 @@ hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n,
                                      const PairParamsHost &pph, hipStream_t s, const int *gate = nullptr);
 // The same for d = 32, 64, 128 (k_sweep_mfma_wide<d>).
 hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
-                                        const PairParamsHost &pph, hipStream_t s);
+                                        const PairParamsHost &pph, hipStream_t s, const int *gate = nullptr);
 // The BF16 path's exact pass over its densely flagged tiles at d = 16, on the matrix cores.
 hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, int n, const GramCtx &gc, float *G,
                                           float *partials, const PairParamsHost &pph, hipStream_t s);

@@ -376,8 +376,10 @@ __global__ __launch_bounds__(64) void k_sweep_wide_list(const float *__restrict_
                                                         const int *__restrict__ list, const int *__restrict__ count,
                                                         float *__restrict__ G, float *__restrict__ rowloss,
                                                         float *__restrict__ partials, PairParams P, float far2,
-                                                        const unsigned char *__restrict__ dense) {
+                                                        const unsigned char *__restrict__ dense,
+                                                        const int *__restrict__ all_dense) {
     extern __shared__ float lds[];
+    if (*all_dense) return;  // the full matrix-core sweep took every tile (uniform over the grid)
     __shared__ float4 ltab[D == 16 ? kLtabF4 : 1];
     if (D == 16) stage_ltab(ltab);  // ordered before use by the tile's first barrier
     const int cnt = *count;
@@ -986,9 +988,10 @@ SweepPlan gempe_make_plan(const gempe_graph_s *g, int d, bool bf16) {
         p.grid = std::min<long long>(p.items, 2048);
         p.edge_blocks = (int)std::max<long long>(1, ((long long)g->n + 3) / 4);  // one wave per row
         p.partials = p.items + p.edge_blocks;
-        // d = 16: an evaluation whose screen flags most tiles (a spread start: nearly every
-        // pair within the near distance) runs the full matrix-core sweep instead of the list
-        if (d == 16 && g->n >= kMfmaMinN) {
+        // d = 16, 32, 64, 128: an evaluation whose screen flags most tiles (d = 16 from a
+        // spread start, any d from a contracted one: nearly every pair within the near
+        // distance) runs the full matrix-core sweep instead of the list
+        if ((d == 16 && g->n >= kMfmaMinN) || ((d == 32 || d == 64 || d == 128) && g->n >= kMfmaWideMinN)) {
             for (int chunk : {32, 16, 8}) {
                 const long long it = gempe_mfma_items(g->n, chunk);
                 const long long grid = (it + kXcd - 1) / kXcd * kXcd;
@@ -1224,7 +1227,7 @@ void launch_wide_list(const SweepPlan &pl, hipStream_t s, const float *X, int n,
         attr_set = true;
     }
     hipLaunchKernelGGL((k_sweep_wide_list<D, EX>), dim3((unsigned)pl.grid), dim3(64), lds, s, X, n, d, pl.nt,
-                       gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0, gc.dense);
+                       gc.list, gc.count, G, rl, part, P, gc.theta0 * gc.theta0, gc.dense, gc.all_dense);
 }
 
 template <int EX>
@@ -1284,20 +1287,22 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
         // four waves per SIMD against the list kernel's three) and the list kernel exits on
         // the sparse pass's flag.  Otherwise, and for per-vertex extras, the LDS tile pass.
         const bool mf16 = EX == kExNone && d == 16 && pph.table_full;
-        const bool full = mf16 && plan.mfma_items > 0;
+        const bool full = EX == kExNone && pph.table_full && plan.mfma_items > 0;
         TimedLaunches tl(kTkExact, s, full ? 3 : 2);
-        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, !mf16 ? 0 : full ? 2 : 1);
-        if (mf16) {
-            if (full) {
-                SweepPlan pm = plan;
-                pm.items = plan.mfma_items;
-                pm.grid = plan.mfma_grid;
+        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, full ? 2 : mf16 ? 1 : 0);
+        if (full) {
+            SweepPlan pm = plan;
+            pm.items = plan.mfma_items;
+            pm.grid = plan.mfma_grid;
+            if (d == 16)
                 (void)gempe_launch_sweep_mfma16(pm, X, n, grad, partials, pph, s, gc.all_dense);
-            }
-            (void)gempe_launch_sweep_mfma16_list(plan, X, n, gc, grad, partials, pph, s);
-        } else {
-            launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
+            else
+                (void)gempe_launch_sweep_mfma_wide(pm, d, X, n, grad, partials, pph, s, gc.all_dense);
         }
+        if (mf16)
+            (void)gempe_launch_sweep_mfma16_list(plan, X, n, gc, grad, partials, pph, s);
+        else
+            launch_list<EX>(plan, s, X, n, d, gc, grad, extra, partials, P);
     } else if (plan.mfma) {
         TimedLaunches tl(kTkSweep, s);
         if (d == 16)

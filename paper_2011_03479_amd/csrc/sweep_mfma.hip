@@ -720,11 +720,15 @@ __device__ float mfma_strip_w(const float *__restrict__ X, int n, int I, int b0,
 
 // d = 32 held to four waves per SIMD (128 VGPRs, a few spilled: 9.5 % faster than three
 // waves without spills); wider d keep the registers their products need
-template <int D>
+// BF: the BF16 path's evaluation whose screen flagged most tiles; it runs only when the
+// sparse pass set *gate (every pair exact in FP32).
+template <int D, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 32 ? 4 : 1))) void k_sweep_mfma_wide(const float *__restrict__ X, int n, int nb, int nJ, int C,
                                                          long long items, long long per_xcd, float *__restrict__ G,
-                                                         float *__restrict__ partials, PairParams P) {
+                                                         float *__restrict__ partials, PairParams P,
+                                                         const int *__restrict__ gate) {
     __shared__ MfLdsW<D> L;
+    if (BF && *gate == 0) return;  // uniform over the grid
     long long t = xcd_item(blockIdx.x, per_xcd);
     if (t >= items) return;  // uniform over the workgroup
     if (P.reverse) t = items - 1 - t;
@@ -774,18 +778,26 @@ hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, i
 }
 
 hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
-                                        const PairParamsHost &pph, hipStream_t s) {
+                                        const PairParamsHost &pph, hipStream_t s, const int *gate) {
     const PairParams P{pph.mu_s,   pph.inv_sigma, pph.c_neg,   pph.c_pos,   pph.tk_scale,   pph.tk_off,
                        pph.slope_k, pph.r_scale,  pph.w_scale, pph.wk2,     pph.table_full, pph.reverse};
     const int nb = (n + 63) / 64;
     const int nJ = (nb + pl.mfma_chunk - 1) / pl.mfma_chunk;
     const long long per = pl.grid / kXcd;
     const dim3 grid((unsigned)pl.grid), block(256);
+#define GEMPE_WIDE(DD)                                                                                          \
+    if (gate)                                                                                                   \
+        hipLaunchKernelGGL((k_sweep_mfma_wide<DD, true>), grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, \
+                           per, G, partials, P, gate);                                                          \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_sweep_mfma_wide<DD, false>), grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk,          \
+                           pl.items, per, G, partials, P, gate)
     switch (d) {
-        case 32: hipLaunchKernelGGL(k_sweep_mfma_wide<32>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
-        case 64: hipLaunchKernelGGL(k_sweep_mfma_wide<64>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
-        case 128: hipLaunchKernelGGL(k_sweep_mfma_wide<128>, grid, block, 0, s, X, n, nb, nJ, pl.mfma_chunk, pl.items, per, G, partials, P); break;
+        case 32: GEMPE_WIDE(32); break;
+        case 64: GEMPE_WIDE(64); break;
+        case 128: GEMPE_WIDE(128); break;
         default: return hipErrorInvalidValue;
     }
+#undef GEMPE_WIDE
     return hipGetLastError();
 }

@@ -160,18 +160,23 @@ def test_bf16_d16_near_edges_cancel():
     assert_grad_close(got["grad"][:16], ref["grad"][:16], ref["abs_slope"][:16], what="bf16 d16 clique vertices")
 
 
-@pytest.mark.parametrize("n,kind", [(9000, "spread"), (8300, "clusters")])
-def test_bf16_d16_full_sweep_route(n, kind):
-    """BF16 at d = 16 from n = 8,192 on.  X ~ N(0, 1): more than half of the tiles are flagged,
-    so the sparse pass hands the evaluation to the full matrix-core sweep (every pair exact in
-    FP32; the dense list kernel exits).  Tight far-apart clusters: most tiles unflagged, the
-    list route.  Both against the whole-graph oracle; the exact pass's launch count shows the
-    route was planned (three launches: sparse pass, full sweep, list)."""
+@pytest.mark.parametrize("n,d,kind", [(9000, 16, "spread"), (8300, 16, "clusters"), (4500, 32, "contracted"),
+                                       (4200, 64, "contracted"), (4300, 64, "clusters")])
+def test_bf16_full_sweep_route(n, d, kind):
+    """BF16 from n = 8,192 (d = 16) or 4,096 (d = 32, 64, 128) on.  When more than half of
+    the tiles are flagged (d = 16 from X ~ N(0, 1), any d from a contracted start) the sparse
+    pass hands the evaluation to the full matrix-core sweep (every pair exact in FP32; the
+    dense list pass exits).  Tight far-apart clusters: most tiles unflagged, the list route.
+    All against the whole-graph oracle; the exact pass's launch count shows the route was
+    planned (three launches: sparse pass, full sweep, list)."""
     if kind == "spread":
         g = synth.chung_lu(n, 10.0, 2.4, seed=n)
-        X = synth.init_embedding(n, 16, seed=n + 1)
+        X = synth.init_embedding(n, d, seed=n + 1)
+    elif kind == "contracted":
+        g = synth.chung_lu(n, 10.0, 2.4, seed=n)
+        X = synth.init_embedding(n, d, seed=n + 1, scale=1.5 / np.sqrt(2 * d))
     else:
-        X, lab = clusters(n, 16, 40, spread=0.1, sep=4.0, seed=n)
+        X, lab = clusters(n, d, 40, spread=0.1, sep=4.0, seed=n)
         order = np.argsort(lab, kind="stable")  # vertices by cluster: far tiles off the diagonal
         X, lab = X[order], lab[order]
         rng = np.random.default_rng(n)
@@ -179,7 +184,7 @@ def test_bf16_d16_full_sweep_route(n, kind):
         members = [np.nonzero(lab == k)[0] for k in range(40)]
         same = np.array([rng.choice(members[lab[a]]) for a in u])
         g = synth.csr_from_edges(n, u, same)
-    note(f"bf16 d16 full-sweep route n={n} {kind} m={g.m}")
+    note(f"bf16 full-sweep route n={n} d={d} {kind} m={g.m}")
     G = gempe.Graph(n, g.row_ptr, g.col_idx)
     gempe.timing_enable(True)
     gempe.timing_read(gempe.GEMPE_TK_EXACT)
@@ -189,8 +194,8 @@ def test_bf16_d16_full_sweep_route(n, kind):
     assert nl == 3, nl
     ref = oracle.loss_grad(X, g.row_ptr, g.col_idx, want_abs_slope=True)
     assert got["edge_hits"] == g.m == ref["edge_hits"]
-    what = f"bf16 d16 route n{n} {kind}"
-    if kind == "spread":
+    what = f"bf16 route n{n} d{d} {kind}"
+    if kind != "clusters":
         # every pair exact in FP32: the FP32 bounds hold
         assert abs(got["loss"] - ref["loss"]) <= 1e-5 * ref["loss"], (what, got["loss"], ref["loss"])
         assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], what=what)
