@@ -421,7 +421,11 @@ enum {
                             gempe_embed call, counted as that many launches)               */
     GEMPE_TK_GRAM = 1,   /* the BF16 MFMA Gram screen                                        */
     GEMPE_TK_EXACT = 2,  /* the exact FP32 passes over the BF16 screen's near tiles          */
-    GEMPE_TK_EDGES = 3   /* the exact edge correction over the CSR entries                  */
+    GEMPE_TK_EDGES = 3,  /* the exact edge correction over the CSR entries                  */
+    GEMPE_TK_FULL = 4    /* the BF16 path's full FP32 matrix-core sweep: launched for plain
+                            evaluations at d = 16 from n = 8,192 and at d = 32, 64, 128 from
+                            n = 4,096; it evaluates every pair when more than half of the
+                            tiles were flagged and returns at once otherwise               */
 };
 
 gempe_status gempe_timing_enable(int32_t on); /* [host] */

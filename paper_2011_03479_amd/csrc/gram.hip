@@ -442,9 +442,10 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lrow = lane & 31, lk = (lane >> 5) * 8;
     const int cnt = *count;
-    // when the dense pass can take any flagged tile (all_dense_ok) and most tiles are flagged
-    // (d = 16 from a spread start: nearly every pair lies within the near distance), every
-    // flagged tile goes to it directly instead of being recomputed here only to be found dense
+    // when the caller allows it (all_dense != 0) and most tiles are flagged (d = 16 from a
+    // spread start, or a contracted embedding at any d: nearly every pair lies within the near
+    // distance), no flagged tile is recomputed here only to be found dense: mode 1 hands each
+    // to the dense list pass, mode 2 leaves every pair to the full matrix-core sweep
     if (all_dense && 2LL * cnt > nb64 * (nb64 + 1) / 2) {
         for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < cnt; q += (long long)gridDim.x * 256) {
             if (all_dense == 1)

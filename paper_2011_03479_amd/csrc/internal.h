@@ -50,7 +50,7 @@ constexpr unsigned long long kHashEmpty = ~0ull;
 
 // Kernel timing brackets (timing.hip); the classes are gempe.h's GEMPE_TK_*.
 enum { kTkSweep = GEMPE_TK_SWEEP, kTkGram = GEMPE_TK_GRAM, kTkExact = GEMPE_TK_EXACT, kTkEdges = GEMPE_TK_EDGES,
-       kTkClasses = 4 };
+       kTkFull = GEMPE_TK_FULL, kTkClasses = 5 };
 bool gempe_timing_on();
 void gempe_timing_begin(int cls, hipStream_t s);
 void gempe_timing_end(int cls, hipStream_t s, int launches);
@@ -198,7 +198,7 @@ struct GramCtx {
     float theta0 = 0.0f;  // mu + near_k sigma
     unsigned char *dense = nullptr;
     int *chunks = nullptr;
-    int *all_dense = nullptr;  // set by the sparse pass when the full d = 16 sweep takes every tile
+    int *all_dense = nullptr;  // set by the sparse pass when the full matrix-core sweep takes every tile
 };
 GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p);
 
@@ -213,7 +213,7 @@ long long gempe_mfma_items(int n, int chunk);
 // gate: the BF16 path's all-dense evaluation (runs only when *gate is set), else null.
 hipError_t gempe_launch_sweep_mfma16(const SweepPlan &pl, const float *X, int n, float *G, float *partials,
                                      const PairParamsHost &pph, hipStream_t s, const int *gate = nullptr);
-// The same for d = 32, 64, 128 (k_sweep_mfma_wide<d>).
+// The same for d = 32, 64, 128 (k_sweep_mfma_wide<d, gated>).
 hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float *X, int n, float *G, float *partials,
                                         const PairParamsHost &pph, hipStream_t s, const int *gate = nullptr);
 // The BF16 path's exact pass over its densely flagged tiles at d = 16, on the matrix cores.
@@ -225,7 +225,7 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
 // Sparse exact pass over the flagged tiles (gram.hip); ex: 0 none, 1 row loss, 2 WM z.
 // all_dense, when more than half of the tiles are flagged: 0 nothing special; 1 every
 // flagged tile is marked dense for the dense pass without being recomputed here; 2 the full
-// d = 16 matrix-core sweep takes every pair (the list's loss slots are cleared and
+// matrix-core sweep (d = 16, 32, 64, 128) takes every pair (the list's loss slots are cleared and
 // *gc.all_dense is set, which the dense pass reads and skips).  *gc.all_dense is 0 otherwise.
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &pp, int ex, float *G, float *extra, float *partials,

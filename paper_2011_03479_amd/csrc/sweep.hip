@@ -1282,15 +1282,19 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
     if (plan.bf16) {
         // The sparse pass evaluates the near pairs of sparsely flagged tiles exactly and marks
         // the dense ones.  At d = 16 the dense tiles of a plain evaluation go to the matrix
-        // cores (FP32 Gram, the exact path for near pairs); from n = 8,192 on, when most
-        // tiles are flagged, the full matrix-core sweep takes every pair instead (chunk-major,
+        // cores (FP32 Gram, the exact path for near pairs).  When most tiles are flagged, a
+        // plain evaluation at d = 16 from n = 8,192 on, or at d = 32, 64, 128 from n = 4,096
+        // on, leaves every pair to the full matrix-core sweep instead (chunk-major; at d = 16
         // four waves per SIMD against the list kernel's three) and the list kernel exits on
         // the sparse pass's flag.  Otherwise, and for per-vertex extras, the LDS tile pass.
         const bool mf16 = EX == kExNone && d == 16 && pph.table_full;
         const bool full = EX == kExNone && pph.table_full && plan.mfma_items > 0;
-        TimedLaunches tl(kTkExact, s, full ? 3 : 2);
-        (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, full ? 2 : mf16 ? 1 : 0);
+        {
+            TimedLaunches tl(kTkExact, s);
+            (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, full ? 2 : mf16 ? 1 : 0);
+        }
         if (full) {
+            TimedLaunches tf(kTkFull, s);
             SweepPlan pm = plan;
             pm.items = plan.mfma_items;
             pm.grid = plan.mfma_grid;
@@ -1299,6 +1303,7 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
             else
                 (void)gempe_launch_sweep_mfma_wide(pm, d, X, n, grad, partials, pph, s, gc.all_dense);
         }
+        TimedLaunches tl(kTkExact, s);
         if (mf16)
             (void)gempe_launch_sweep_mfma16_list(plan, X, n, gc, grad, partials, pph, s);
         else

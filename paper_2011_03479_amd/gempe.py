@@ -259,6 +259,7 @@ GEMPE_TK_SWEEP = 0
 GEMPE_TK_GRAM = 1
 GEMPE_TK_EXACT = 2
 GEMPE_TK_EDGES = 3
+GEMPE_TK_FULL = 4
 
 
 def timing_enable(on: bool = True):
