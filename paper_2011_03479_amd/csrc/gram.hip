@@ -74,8 +74,9 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ X, 
 
 // Largest |x| of every 128-vertex block (for the per-tile threshold of the screen).
 __global__ __launch_bounds__(128) void k_blockmax(const float *__restrict__ snorm, int n,
-                                                  float *__restrict__ smax128) {
+                                                  float *__restrict__ smax128, int *__restrict__ sample) {
     __shared__ float w[2];
+    if (sample && blockIdx.x == 0 && threadIdx.x < 2) sample[threadIdx.x] = 0;  // the route sample's counts
     const int v = blockIdx.x * 128 + threadIdx.x;
     float s = v < n ? snorm[v] : 0.0f;
 #pragma unroll
@@ -96,14 +97,25 @@ __global__ __launch_bounds__(128) void k_blockmax(const float *__restrict__ snor
 // 256 registers: two per SIMD, so one wave's MFMAs cover the other's waits.  Writes
 // flags[t64] (1: some pair of the 64 x 64 sub-tile may be near) for every sub-tile on or
 // above the diagonal, so the flags need no clearing between calls.
+// The route sample runs the same kernel on every sstride-th strip, one item per strip (qb = 1)
+// with a column step Q larger than the screen's and a phase that turns from strip to strip,
+// and counts its sub-tiles and their flags into sample[0..1].  The screen after it returns at once when gate (those counts) shows more than
+// half of the sampled sub-tiles flagged: the full matrix-core sweep then takes every pair.
 constexpr int kScreenThreads = 512;
+
+// More than half of the route sample's sub-tiles flagged (read by every kernel it gates).
+__device__ __forceinline__ bool sample_dense(const int *sample) {
+    return sample && 2LL * sample[0] > (long long)sample[1];
+}
 
 template <int D, int RW>
 __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__restrict__ Xb,
                                                      const float *__restrict__ nrm,
                                                      const float *__restrict__ smax128, int n, int ntile,
                                                      int Q, long long nb64, float theta0,
-                                                     unsigned char *__restrict__ flags) {
+                                                     unsigned char *__restrict__ flags, int qb, int sstride,
+                                                     const int *__restrict__ gate, int *__restrict__ sample) {
+    if (sample_dense(gate)) return;  // uniform over the grid
     constexpr int CW = 8 / RW;
     constexpr int S = D + 8;   // padded LDS row stride (bf16): rows fall on different banks
     constexpr int CH = D / 8;  // 16-byte chunks per row
@@ -116,7 +128,9 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: branches stay scalar
-    const int I = blockIdx.x / Q, q = blockIdx.x % Q;
+    // the screen: qb = Q items per strip, phases q = 0 .. Q - 1; the sample: one item per
+    // strip, its phase turning with the strip, so that every column tile is equally likely
+    const int I = (int)(blockIdx.x / qb) * sstride, q = (int)(blockIdx.x % Q);
     int J = (I * RW) / CW + q;
     if (J >= ntile) return;  // uniform over the workgroup
     const int wr = wave / CW, wc = wave % CW;
@@ -239,7 +253,13 @@ __global__ __launch_bounds__(kScreenThreads) void k_gram_screen(const __bf16 *__
             near = near || (m > hb_of(b));
         }
         const bool any = __ballot(near) != 0ull;
-        if (lane == 0) flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
+        if (lane == 0) {
+            flags[upper_index(R64, C64, nb64)] = any ? 1 : 0;
+            if (sample) {
+                atomicAdd(&sample[0], any ? 1 : 0);
+                atomicAdd(&sample[1], 1);
+            }
+        }
     };
     // the late waves' sub-tile held over to the next step, with its thresholds (its LDS
     // buffer is refilled after the next barrier)
@@ -350,7 +370,8 @@ __device__ __forceinline__ int flags_in_word(const uint4 &w, long long base, lon
 constexpr int kChunkFlags = 4096;  // 256 threads x 16 flags (one uint4 each)
 
 __global__ __launch_bounds__(256) void k_flag_count(const unsigned char *__restrict__ flags, long long total,
-                                                    int *__restrict__ chunk_count) {
+                                                    int *__restrict__ chunk_count, const int *__restrict__ gate) {
+    if (sample_dense(gate)) return;
     __shared__ int ws[4];
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;  // uint4 word index
     int c = 0;
@@ -365,7 +386,9 @@ __global__ __launch_bounds__(256) void k_flag_count(const unsigned char *__restr
     if (threadIdx.x == 0) chunk_count[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
-__global__ __launch_bounds__(1024) void k_flag_scan(int *__restrict__ chunk_count, int chunks, int *__restrict__ count) {
+__global__ __launch_bounds__(1024) void k_flag_scan(int *__restrict__ chunk_count, int chunks, int *__restrict__ count,
+                                                    const int *__restrict__ gate) {
+    if (sample_dense(gate)) return;
     __shared__ int sc[1024];
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
@@ -390,7 +413,9 @@ __global__ __launch_bounds__(1024) void k_flag_scan(int *__restrict__ chunk_coun
 }
 
 __global__ __launch_bounds__(256) void k_flag_write(const unsigned char *__restrict__ flags, long long total,
-                                                    const int *__restrict__ chunk_offset, int *__restrict__ list) {
+                                                    const int *__restrict__ chunk_offset, int *__restrict__ list,
+                                                    const int *__restrict__ gate) {
+    if (sample_dense(gate)) return;
     __shared__ int sc[256];
     const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
     uint4 w = {0u, 0u, 0u, 0u};
@@ -432,11 +457,21 @@ __global__ __launch_bounds__(256) void k_near_tiles(const __bf16 *__restrict__ X
                                                     const float *__restrict__ nrm,
                                                     const float *__restrict__ smax128, int n, long long nb64,
                                                     float theta0, const int *__restrict__ list,
-                                                    const int *__restrict__ count, gempe::PairParams P,
+                                                    int *__restrict__ count, gempe::PairParams P,
                                                     float *__restrict__ G, float *__restrict__ extra,
                                                     float *__restrict__ partials,
                                                     unsigned char *__restrict__ dense, int all_dense,
-                                                    int *__restrict__ all_dense_flag) {
+                                                    int *__restrict__ all_dense_flag, const int *__restrict__ sample,
+                                                    int full_items) {
+    if (sample_dense(sample)) {
+        // the route sample found most tiles flagged and the screen did not run: the full
+        // sweep writes loss slots [0, full_items), which the reduction then sums
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *all_dense_flag = 1;
+            *count = full_items;
+        }
+        return;
+    }
     __shared__ int near[4][kSparseNear];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -586,12 +621,12 @@ using namespace gempe;
 
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
-                                    float theta0, int *chunk, hipStream_t s) {
+                                    float theta0, int *chunk, hipStream_t s, int *sample) {
     const int n = g->n;
     hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d,
                        reinterpret_cast<__bf16 *>(Xb), nrm, snorm);
     const int nt128 = (n + 127) / 128;
-    hipLaunchKernelGGL(k_blockmax, dim3((unsigned)nt128), dim3(128), 0, s, snorm, n, smax128);
+    hipLaunchKernelGGL(k_blockmax, dim3((unsigned)nt128), dim3(128), 0, s, snorm, n, smax128, sample);
     const long long nb64 = (n + 63) / 64;
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(Xb);
     // 512-row strips once there are enough of them to fill the chip with Q = 8 column
@@ -600,16 +635,30 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
     const int RW = tall ? 8 : 2, TC = 64 * (8 / RW);
     const int nstrip = (n + 64 * RW - 1) / (64 * RW), ntile = (n + TC - 1) / TC;
     const int Q = tall ? 8 : std::max(1, std::min(8, ntile / 2));
-    dim3 grid((unsigned)((long long)nstrip * Q)), block(kScreenThreads);
-#define GEMPE_SCREEN(DD)                                                                                          \
-    if (tall)                                                                                                     \
-        hipLaunchKernelGGL((k_gram_screen<DD, 8>), grid, block, 0, s, xb, nrm, smax128, n, ntile, Q, nb64, theta0, \
-                           flags);                                                                                \
-    else                                                                                                          \
-        hipLaunchKernelGGL((k_gram_screen<DD, 2>), grid, block, 0, s, xb, nrm, smax128, n, ntile, Q, nb64, theta0, \
-                           flags)
+    // the route sample: about 32 strips spread over the matrix, each against every Qs-th
+    // column tile right of its diagonal (phase k mod Qs for the k-th sampled strip)
+    const int sstride = std::max(1, nstrip / 32);
+    const int Qs = std::max(Q, std::min(16 * Q, ntile / 8));
+#define GEMPE_SCREEN_GRID(DD, G, QQ, QB, SS, GATE, SAMPLE)                                                      \
+    do {                                                                                                        \
+        if (tall)                                                                                               \
+            hipLaunchKernelGGL((k_gram_screen<DD, 8>), G, dim3(kScreenThreads), 0, s, xb, nrm, smax128, n, ntile, \
+                               QQ, nb64, theta0, flags, QB, SS, GATE, SAMPLE);                                 \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_gram_screen<DD, 2>), G, dim3(kScreenThreads), 0, s, xb, nrm, smax128, n, ntile, \
+                               QQ, nb64, theta0, flags, QB, SS, GATE, SAMPLE);                                 \
+    } while (0)
+#define GEMPE_SCREEN(DD)                                                                                        \
+    do {                                                                                                        \
+        if (sample) {                                                                                           \
+            GEMPE_SCREEN_GRID(DD, dim3((unsigned)((nstrip + sstride - 1) / sstride)), Qs, 1, sstride,           \
+                              (const int *)nullptr, sample);                                                    \
+        }                                                                                                       \
+        TimedLaunches tl(kTkGram, s);                                                                           \
+        GEMPE_SCREEN_GRID(DD, dim3((unsigned)((long long)nstrip * Q)), Q, Q, 1, (const int *)sample,             \
+                          (int *)nullptr);                                                                      \
+    } while (0)
     {
-        TimedLaunches tl(kTkGram, s);
         switch (d) {
             case 16: GEMPE_SCREEN(16); break;
             case 32: GEMPE_SCREEN(32); break;
@@ -622,24 +671,28 @@ hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *
         }
     }
 #undef GEMPE_SCREEN
+#undef GEMPE_SCREEN_GRID
     const long long t64 = nb64 * (nb64 + 1) / 2;
     const int chunks = (int)((t64 + kChunkFlags - 1) / kChunkFlags);
-    hipLaunchKernelGGL(k_flag_count, dim3(chunks), dim3(256), 0, s, flags, t64, chunk);
-    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, chunk, chunks, count);
-    hipLaunchKernelGGL(k_flag_write, dim3(chunks), dim3(256), 0, s, flags, t64, chunk, list);
+    const int *gate = sample;
+    hipLaunchKernelGGL(k_flag_count, dim3(chunks), dim3(256), 0, s, flags, t64, chunk, gate);
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, s, chunk, chunks, count, gate);
+    hipLaunchKernelGGL(k_flag_write, dim3(chunks), dim3(256), 0, s, flags, t64, chunk, list, gate);
     return hipGetLastError();
 }
 
 namespace {
 template <int EX>
 void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc, const gempe::PairParams &P,
-                          float *G, float *extra, float *partials, hipStream_t s, int all_dense) {
+                          float *G, float *extra, float *partials, hipStream_t s, int all_dense,
+                          const int *sample, int full_items) {
     const long long nb64 = (g->n + 63) / 64;
     const __bf16 *xb = reinterpret_cast<const __bf16 *>(gc.xb);
     const dim3 grid(kNearTileGrid), block(256);
 #define GEMPE_NEAR(DD)                                                                                     \
     hipLaunchKernelGGL((k_near_tiles<DD, EX>), grid, block, 0, s, xb, X, gc.nrm, gc.smax128, g->n, nb64,  \
-                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense, all_dense, gc.all_dense)
+                       gc.theta0, gc.list, gc.count, P, G, extra, partials, gc.dense, all_dense, gc.all_dense, \
+                       sample, full_items)
     switch (d) {
         case 16: GEMPE_NEAR(16); break;
         case 32: GEMPE_NEAR(32); break;
@@ -656,14 +709,14 @@ void launch_near_tiles_ex(const gempe_graph_s *g, int d, const float *X, const G
 
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &h, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s, int all_dense) {
+                                   hipStream_t s, int all_dense, const int *sample, int full_items) {
     const gempe::PairParams P{h.mu_s,   h.inv_sigma, h.c_neg,   h.c_pos,   h.tk_scale,
                               h.tk_off, h.slope_k,   h.r_scale, h.w_scale, h.wk2, h.table_full, 0};
     if (ex == 2)
-        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s, all_dense);
+        launch_near_tiles_ex<2>(g, d, X, gc, P, G, extra, partials, s, all_dense, sample, full_items);
     else if (ex == 1)
-        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s, all_dense);
+        launch_near_tiles_ex<1>(g, d, X, gc, P, G, extra, partials, s, all_dense, sample, full_items);
     else
-        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s, all_dense);
+        launch_near_tiles_ex<0>(g, d, X, gc, P, G, extra, partials, s, all_dense, sample, full_items);
     return hipGetLastError();
 }

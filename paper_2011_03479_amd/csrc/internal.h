@@ -152,7 +152,8 @@ long long gempe_shard_items(int nt, int s, int G);
 
 struct WsLayout {
     size_t counters = 0;  // 256 B: [0] int64 edge hits, [8] unsigned status, [16] FP64 loss
-                          // scratch, [32] int flagged-tile count, [36] int all-dense flag (BF16)
+                          // scratch, [32] int flagged-tile count, [36] int all-dense flag,
+                          // [40] int x 2 the route sample's flagged and sampled sub-tiles (BF16)
     size_t partials = 0;  // float[plan.partials]
     size_t gbuf = 0;      // float[n*d] gradient scratch for gempe_step/gempe_embed
     size_t zbuf = 0;      // float[n] weighted-majorization denominators z_i
@@ -199,6 +200,7 @@ struct GramCtx {
     unsigned char *dense = nullptr;
     int *chunks = nullptr;
     int *all_dense = nullptr;  // set by the sparse pass when the full matrix-core sweep takes every tile
+    int *sample = nullptr;     // the route sample's flagged and sampled sub-tile counts (two ints)
 };
 GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params *p);
 
@@ -219,17 +221,23 @@ hipError_t gempe_launch_sweep_mfma_wide(const SweepPlan &pl, int d, const float 
 // The BF16 path's exact pass over its densely flagged tiles at d = 16, on the matrix cores.
 hipError_t gempe_launch_sweep_mfma16_list(const SweepPlan &pl, const float *X, int n, const GramCtx &gc, float *G,
                                           float *partials, const PairParamsHost &pph, hipStream_t s);
+// sample: null, or the route sample's counters (GramCtx::sample).  With them a sample of the
+// tiles is screened first, and when more than half of it is flagged the screen and the flag
+// compaction return at once (the full matrix-core sweep takes the evaluation).
 hipError_t gempe_launch_gram_screen(const gempe_graph_s *g, int d, const float *X, void *Xb, float *nrm,
                                     float *snorm, float *smax128, unsigned char *flags, int *list, int *count,
-                                    float theta0, int *chunk, hipStream_t s);
+                                    float theta0, int *chunk, hipStream_t s, int *sample = nullptr);
 // Sparse exact pass over the flagged tiles (gram.hip); ex: 0 none, 1 row loss, 2 WM z.
 // all_dense, when more than half of the tiles are flagged: 0 nothing special; 1 every
 // flagged tile is marked dense for the dense pass without being recomputed here; 2 the full
 // matrix-core sweep (d = 16, 32, 64, 128) takes every pair (the list's loss slots are cleared and
 // *gc.all_dense is set, which the dense pass reads and skips).  *gc.all_dense is 0 otherwise.
+// sample: the counters the screen was launched with (or null); when they show most sampled
+// tiles flagged the pass only sets *gc.all_dense and the loss-slot count to full_items.
 hipError_t gempe_launch_near_tiles(const gempe_graph_s *g, int d, const float *X, const GramCtx &gc,
                                    const PairParamsHost &pp, int ex, float *G, float *extra, float *partials,
-                                   hipStream_t s, int all_dense = 0);
+                                   hipStream_t s, int all_dense = 0, const int *sample = nullptr,
+                                   int full_items = 0);
 hipError_t gempe_launch_axpy(float *X, const float *G, float eta, long long count, hipStream_t s);
 hipError_t gempe_launch_wm_update(float *X, const float *G, const float *Z, int d, long long count, hipStream_t s);
 // Continuous batching of fused iterations (sweep.hip): one table row per job.

@@ -1154,6 +1154,7 @@ GramCtx gempe_gram_ctx(const WsLayout &L, unsigned char *ws, const gempe_params 
     c.dense = ws + L.dense;
     c.chunks = reinterpret_cast<int *>(ws + L.chunks);
     c.all_dense = reinterpret_cast<int *>(ws + L.counters + 36);
+    c.sample = reinterpret_cast<int *>(ws + L.counters + 40);
     c.theta0 = (float)(p->mu + p->near_k * p->sigma);
     return c;
 }
@@ -1272,6 +1273,15 @@ void launch_iters(const SweepPlan &pl, IterArgs &a, int K, int iters, hipStream_
 }  // namespace
 
 namespace {
+// The BF16 path's route sample: at d = 16 the screen costs a tenth of the FP32 sweep it would
+// spare, so a plain evaluation that may take the full matrix-core route screens a sample of
+// its tiles first and skips the screen when most of the sample is flagged (the full sweep is
+// exact for every pair, so only the time depends on the sample).  At d >= 32 the screen is
+// under 2 % of that sweep and always runs.
+bool route_sample(const SweepPlan &plan, int d, bool plain, const PairParamsHost &pph) {
+    return plan.bf16 && plain && pph.table_full && plan.mfma_items > 0 && d == 16;
+}
+
 // The sweep (or BF16 screen + exact list pass) and the exact edge correction, with the
 // per-vertex extra sum EX into `extra` (row loss or the weighted-majorization z).
 template <int EX>
@@ -1291,7 +1301,9 @@ void launch_pass(const gempe_graph_s *g, int d, const SweepPlan &plan, const flo
         const bool full = EX == kExNone && pph.table_full && plan.mfma_items > 0;
         {
             TimedLaunches tl(kTkExact, s);
-            (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, full ? 2 : mf16 ? 1 : 0);
+            const int *sample = route_sample(plan, d, EX == kExNone, pph) ? gc.sample : nullptr;
+            (void)gempe_launch_near_tiles(g, d, X, gc, pph, EX, grad, extra, partials, s, full ? 2 : mf16 ? 1 : 0,
+                                          sample, (int)plan.mfma_items);
         }
         if (full) {
             TimedLaunches tf(kTkFull, s);
@@ -1374,8 +1386,10 @@ hipError_t gempe_launch_loss_grad(const gempe_graph_s *g, int d, const SweepPlan
                            clear_status ? 2 : 1);
     }
     if (plan.bf16) {
+        const bool plain = !row_loss && !wm_z;
         hipError_t e = gempe_launch_gram_screen(g, d, X, gc.xb, gc.nrm, gc.snorm, gc.smax128, gc.flags, gc.list,
-                                                gc.count, gc.theta0, gc.chunks, s);
+                                                gc.count, gc.theta0, gc.chunks, s,
+                                                route_sample(plan, d, plain, pph) ? gc.sample : nullptr);
         if (e != hipSuccess) return e;
     }
     if (wm_z)

@@ -206,3 +206,53 @@ def test_bf16_full_sweep_route(n, d, kind):
         assert_grad_close(got["grad"], ref["grad"], ref["abs_slope"], rtol=BF16_GRAD_RTOL, what=what,
                           atol=(n - 1) * BF16_FLUSH_GRAD)
     G.close()
+
+
+def test_bf16_route_sample_alternating():
+    """At d = 16 a plain BF16 evaluation that may take the full matrix-core route screens a
+    sample of its tiles first and skips the screen when most of the sample is flagged.  One
+    graph and one workspace, evaluated from a spread start (the sample is dense: no screen,
+    the full sweep) and from tight far-apart clusters (the sample is sparse: the screen and
+    the list route) in turn, so each evaluation starts from the other route's leftover
+    flags, list, counts and loss slots; every one against the whole-graph oracle, and the
+    repeats' losses bit for bit equal to the first ones (fixed-order loss sums)."""
+    n, d = 8300, 16
+    Xc, lab = clusters(n, d, 40, spread=0.1, sep=4.0, seed=7)
+    order = np.argsort(lab, kind="stable")
+    Xc, lab = Xc[order], lab[order]
+    rng = np.random.default_rng(8)
+    u = rng.integers(0, n, 3 * n)
+    members = [np.nonzero(lab == k)[0] for k in range(40)]
+    same = np.array([rng.choice(members[lab[a]]) for a in u])
+    g = synth.csr_from_edges(n, u, same)
+    Xs = synth.init_embedding(n, d, seed=9)
+    note(f"bf16 route sample alternating n={n} d={d} m={g.m}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    params = gempe.params_default(**BF16)
+    ws = gempe.workspace(G, d, params)
+    refs = {"spread": oracle.loss_grad(Xs, g.row_ptr, g.col_idx, want_abs_slope=True),
+            "clusters": oracle.loss_grad(Xc, g.row_ptr, g.col_idx, want_abs_slope=True)}
+    first = {}
+    for kind in ("clusters", "spread", "clusters", "spread", "spread", "clusters"):
+        X = Xs if kind == "spread" else Xc
+        r = gempe.loss_grad(G, to_dev(X), ws=ws, params=params)
+        torch.cuda.synchronize()
+        loss, grad = float(r.loss.item()), r.grad.double().cpu().numpy()
+        # the route the sample chose: the workspace opens with the library's counter block,
+        # whose bytes 40..47 hold the sample's flagged and sampled sub-tile counts
+        flagged, sampled = (int(v) for v in ws[40:48].cpu().view(torch.int32))
+        assert sampled > 0 and (2 * flagged > sampled) == (kind == "spread"), (kind, flagged, sampled)
+        ref = refs[kind]
+        assert int(r.edge_hits.item()) == g.m == ref["edge_hits"]
+        what = f"route sample {kind}"
+        if kind == "spread":  # every pair exact in FP32
+            assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"], (what, loss, ref["loss"])
+            assert_grad_close(grad, ref["grad"], ref["abs_slope"], what=what)
+        else:
+            assert abs(loss - ref["loss"]) <= BF16_LOSS_RTOL * ref["loss"], (what, loss, ref["loss"])
+            assert_grad_close(grad, ref["grad"], ref["abs_slope"], rtol=BF16_GRAD_RTOL, what=what,
+                              atol=(n - 1) * BF16_FLUSH_GRAD)
+        if kind in first:
+            assert loss == first[kind], (what, loss, first[kind])
+        first.setdefault(kind, loss)
+    G.close()
