@@ -40,14 +40,28 @@
 
 namespace gempe {
 
-// The two-float4 form (pair_nonedge_tab2) of the same table: 2 kLtabF4 float4.
-__device__ __forceinline__ void stage_ltab2(float4 *dst, float slope_k) {
+// The two-float4 form (pair_nonedge_tab2) of the same table: 2 kLtabF4 float4, staged by a
+// workgroup of 256 threads in two halves, so that other loads can be issued between them:
+// ltab2_load reads this thread's entries, ltab2_store writes them to LDS.
+constexpr int kLtab2Per = (kLtabF4 + 255) / 256;
+__device__ __forceinline__ void ltab2_load(float4 (&c)[kLtab2Per]) {
     const float4 *src = reinterpret_cast<const float4 *>(kLtab);
-    for (int q = threadIdx.x; q < kLtabF4; q += blockDim.x) {
-        const float4 c = src[q];
-        const float n0 = rintf(c.x);
-        dst[2 * q] = make_float4(__int_as_float((int)n0), c.x - n0, c.y, c.z);
-        dst[2 * q + 1] = make_float4(c.w, slope_k * c.y, slope_k * (2.0f * c.z), slope_k * (3.0f * c.w));
+#pragma unroll
+    for (int r = 0; r < kLtab2Per; ++r) {
+        const int q = (int)threadIdx.x + 256 * r;
+        c[r] = src[q < kLtabF4 ? q : kLtabF4 - 1];
+    }
+}
+__device__ __forceinline__ void ltab2_store(float4 *dst, const float4 (&c)[kLtab2Per], float slope_k) {
+#pragma unroll
+    for (int r = 0; r < kLtab2Per; ++r) {
+        const int q = (int)threadIdx.x + 256 * r;
+        if (q < kLtabF4) {
+            const float n0 = rintf(c[r].x);
+            dst[2 * q] = make_float4(__int_as_float((int)n0), c[r].x - n0, c[r].y, c[r].z);
+            dst[2 * q + 1] =
+                make_float4(c[r].w, slope_k * c[r].y, slope_k * (2.0f * c[r].z), slope_k * (3.0f * c[r].w));
+        }
     }
 }
 
@@ -746,16 +760,21 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const long long nd = (long long)a.n * a.d;
-    float *Xs[2] = {a.Xc, a.Xw};
-    const float *Xprev = (k == 0) ? a.Xc : Xs[(k - 1) & 1];
+    // iterate slots by selection, not through an indexed array of pointers (which would
+    // turn every coordinate access into a flat access)
+    float *Xcur = (k & 1) ? a.Xw : a.Xc;
+    const float *Xprev = (k == 0 || !((k - 1) & 1)) ? a.Xc : a.Xw;
     const float *Gprev = (k == 0) ? nullptr : a.G0 + (size_t)((k - 1) % 3) * nd;
     float *Gk = a.G0 + (size_t)(k % 3) * nd;
     float *Gnext = a.G0 + (size_t)((k + 1) % 3) * nd;
     float *Pk = a.P0 + (size_t)(k & 1) * a.units;
     const XView xv{Xprev, Gprev, a.neg_eta, a.d};
 
+    // x_k = x_{k-1} - eta g_{k-1} stored for the caller and the next slot of gradients
+    // cleared (nothing in this launch reads either; done last, behind the sweep, this
+    // measured 2 us slower per launch)
     for (long long v = gtid; v < nd; v += nthreads) {
-        if (k > 0) Xs[k & 1][v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
+        if (k > 0) Xcur[v] = __builtin_fmaf(a.neg_eta, Gprev[v], Xprev[v]);
         Gnext[v] = 0.0f;
     }
     if (b >= a.units) {  // uniform over the workgroup
@@ -764,11 +783,44 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
         if (b == a.units && k > 0) reduce_loss(a, k - 1, sh);
         return;
     }
-    stage_ltab2(L.tab, a.P.slope_k);
+    // the table's loads and a tile workgroup's operand loads are all issued before the
+    // first of them is waited for, so their latencies overlap
+    float4 tabc[kLtab2Per];
+    ltab2_load(tabc);
+    const bool tile = b >= a.units_edge;  // uniform over the workgroup
+    const int dir = rot_dir(lane);
+    const int t = a.P.reverse ? (int)(a.units - 1 - b) : b - (int)a.units_edge;
+    int I = 0, J = 0;
+    if (tile) tile_of(t, a.nb, I, J);
+    const int i = I * 64 + lane;
+    const int col0 = J * 64;
+    const int s0 = wave * 16;
+    const int jc = col0 + ((lane + dir * s0) & 63);
+    // every load at a clamped in-range index, all issued before the first is used
+    float xi[1][D], xc[D];
+    {
+        const size_t oi = (size_t)min(i, a.n - 1) * a.d, oj = (size_t)min(jc, a.n - 1) * a.d;
+        float gi0[D], gc0[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const int qq = min(q, a.d - 1);
+            xi[0][q] = Xprev[oi + qq];
+            xc[q] = Xprev[oj + qq];
+            gi0[q] = Gprev ? Gprev[oi + qq] : 0.0f;
+            gc0[q] = Gprev ? Gprev[oj + qq] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const bool qd = tile && q < a.d;
+            xi[0][q] = (qd && i < a.n) ? __builtin_fmaf(a.neg_eta, gi0[q], xi[0][q]) : 0.0f;
+            xc[q] = (qd && jc < a.n) ? __builtin_fmaf(a.neg_eta, gc0[q], xc[q]) : 0.0f;
+        }
+    }
+    ltab2_store(L.tab, tabc, a.P.slope_k);
     __syncthreads();
     float loss = 0.0f;
     int slot = b;
-    if (b < a.units_edge) {
+    if (!tile) {
         // edge workgroups come first: their dependent gathers overlap the tiles
         const long long e0 = ((long long)b * 4 + wave) * a.epu;
         for (int q = 0; q < a.epu; q += 64) {
@@ -794,21 +846,11 @@ __device__ __forceinline__ void iter_body(const IterArgs &a, int k, int b, long 
     } else {
         // one 64 x 64 tile per workgroup; wave w runs steps [16 w, 16 w + 16) of the
         // schedule, the four waves' row and column partials meet in LDS
-        const int dir = rot_dir(lane);
-        const int t = a.P.reverse ? (int)(a.units - 1 - b) : b - (int)a.units_edge;
         slot = (int)a.units_edge + t;  // the loss partial of tile t, whichever workgroup runs it
-        int I, J;
-        tile_of(t, a.nb, I, J);
-        const int i = I * 64 + lane;
-        const int col0 = J * 64;
-        const int s0 = wave * 16;
-        const int jc = col0 + ((lane + dir * s0) & 63);
-        float xi[1][D], xc[D], gi[1][D], li[1], colacc[D];
+        float gi[1][D], li[1], colacc[D];
         int irow[1] = {i};
 #pragma unroll
         for (int q = 0; q < D; ++q) {
-            xi[0][q] = (i < a.n && q < a.d) ? xv.at(i, q) : 0.0f;
-            xc[q] = (jc < a.n && q < a.d) ? xv.at(jc, q) : 0.0f;
             gi[0][q] = 0.0f;
             colacc[q] = 0.0f;
         }
