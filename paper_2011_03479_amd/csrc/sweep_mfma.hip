@@ -615,17 +615,18 @@ __device__ __forceinline__ void mfma_block_w(const float *__restrict__ X, int n,
         }
         __builtin_amdgcn_wave_barrier();
         // the four waves' partials of these 16 columns, summed in wave order:
-        // g_j += T_j x_j - sum_i cc_ij x_i
+        // g_j += T_j x_j - sum_i cc_ij x_i (the loop unrolled, so that each thread's LDS
+        // reads are issued together instead of one iteration's at a time)
         __syncthreads();
-        for (int k = threadIdx.x; k < 16 * D; k += 256) {
+#pragma unroll
+        for (int it = 0; it < 16 * D / 256; ++it) {
+            const int k = (int)threadIdx.x + 256 * it;
             const int col = k / D, kk = k - col * D, jj = j0 + 16 * q + col;
-            if (jj < n) {
-                const int o = col * (D + 1);
-                const float cs = (L.colq[0][o + kk] + L.colq[1][o + kk]) + (L.colq[2][o + kk] + L.colq[3][o + kk]);
-                const float ts = (L.colq[0][o + D] + L.colq[1][o + D]) + (L.colq[2][o + D] + L.colq[3][o + D]);
-                const float xj = L.ycol[(16 * q + col) * kS + (kk & ~15) + perm16(kk & 15)];
-                atomicAdd(&G[(size_t)jj * D + kk], __builtin_fmaf(ts, xj, -cs) * kCUnscale);
-            }
+            const int o = col * (D + 1);
+            const float cs = (L.colq[0][o + kk] + L.colq[1][o + kk]) + (L.colq[2][o + kk] + L.colq[3][o + kk]);
+            const float ts = (L.colq[0][o + D] + L.colq[1][o + D]) + (L.colq[2][o + D] + L.colq[3][o + D]);
+            const float xj = L.ycol[(16 * q + col) * kS + (kk & ~15) + perm16(kk & 15)];
+            if (jj < n) atomicAdd(&G[(size_t)jj * D + kk], __builtin_fmaf(ts, xj, -cs) * kCUnscale);
         }
         __syncthreads();  // the slots are rewritten by the next column group
     }
@@ -678,11 +679,14 @@ __device__ float mfma_strip_w(const float *__restrict__ X, int n, int I, int b0,
             dst[perm16(k0 + 3)] = v.w;
         }
         __syncthreads();
-        if (threadIdx.x < 64) {  // squared norms of the staged columns
-            const float *yc = L.ycol + threadIdx.x * kS;
+        {  // squared norms of the staged columns: four quarter sums per column, combined in order
+            const float *yc = L.ycol + (threadIdx.x >> 2) * kS + (threadIdx.x & 3) * (D / 4);
             float sq = 0.0f;
-            for (int k = 0; k < D; ++k) sq = __builtin_fmaf(yc[k], yc[k], sq);
-            L.ynrm[threadIdx.x] = sq;
+#pragma unroll 8
+            for (int k = 0; k < D / 4; ++k) sq = __builtin_fmaf(yc[k], yc[k], sq);
+            sq += __shfl_xor(sq, 1, 64);
+            sq += __shfl_xor(sq, 2, 64);
+            if ((threadIdx.x & 3) == 0) L.ynrm[threadIdx.x >> 2] = sq;
         }
         __syncthreads();
         const bool masked = (b == I) || (j0 + 64 > n) || (I * 64 + 64 > n);
@@ -719,11 +723,12 @@ __device__ float mfma_strip_w(const float *__restrict__ X, int n, int I, int b0,
 }  // namespace
 
 // d = 32 held to four waves per SIMD (128 VGPRs, a few spilled: 9.5 % faster than three
-// waves without spills); wider d keep the registers their products need
+// waves without spills), d = 64 to three and d = 128 to two (the unrolled column flush would
+// otherwise take the registers of a wave; a few values spill instead)
 // BF: the BF16 path's evaluation whose screen flagged most tiles; it runs only when the
 // sparse pass set *gate (every pair exact in FP32).
 template <int D, bool BF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 32 ? 4 : 1))) void k_sweep_mfma_wide(const float *__restrict__ X, int n, int nb, int nJ, int C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 32 ? 4 : D == 64 ? 3 : 2))) void k_sweep_mfma_wide(const float *__restrict__ X, int n, int nb, int nJ, int C,
                                                          long long items, long long per_xcd, float *__restrict__ G,
                                                          float *__restrict__ partials, PairParams P,
                                                          const int *__restrict__ gate) {
