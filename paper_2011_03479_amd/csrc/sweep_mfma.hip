@@ -352,17 +352,19 @@ __device__ float mfma_strip(const float *__restrict__ X, int n, int I, int b0, i
                                      S, lblk, G, P, L.ltab, tko, far2, g, c);
         loss += lblk * kCUnscale;
         __syncthreads();
-        // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order
-        for (int k = threadIdx.x; k < 64 * 16; k += 256) {
+        // g_j += T_j x_j - sum_i cc_ij x_i, the four waves' partials summed in wave order (two
+        // elements' LDS reads issued together; unrolled whole, the loop spills at 128 VGPRs)
+#pragma unroll 2
+        for (int it = 0; it < 4; ++it) {
+            const int k = (int)threadIdx.x + 256 * it;
             const int col = k >> 4, kk = k & 15, j = j0 + col;
-            if (j < n) {
-                const float cs = (L.colp[0][col * 17 + kk] + L.colp[1][col * 17 + kk]) +
-                                 (L.colp[2][col * 17 + kk] + L.colp[3][col * 17 + kk]);
-                const float ts = (L.colp[0][col * 17 + 16] + L.colp[1][col * 17 + 16]) +
-                                 (L.colp[2][col * 17 + 16] + L.colp[3][col * 17 + 16]);
+            const float cs = (L.colp[0][col * 17 + kk] + L.colp[1][col * 17 + kk]) +
+                             (L.colp[2][col * 17 + kk] + L.colp[3][col * 17 + kk]);
+            const float ts = (L.colp[0][col * 17 + 16] + L.colp[1][col * 17 + 16]) +
+                             (L.colp[2][col * 17 + 16] + L.colp[3][col * 17 + 16]);
+            if (j < n)
                 atomicAdd(&G[(size_t)j * 16 + kk],
                           __builtin_fmaf(ts, L.ycol[col * kMS + perm16(kk)], -cs) * kCUnscale);
-            }
         }
     }
     // g_i += S_i x_i - sum_j cc_ij x_j: lane (g, c) holds coordinates 4g .. 4g+3 of row r0 + c
