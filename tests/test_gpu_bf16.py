@@ -161,7 +161,7 @@ def test_bf16_d16_near_edges_cancel():
 
 
 @pytest.mark.parametrize("n,d,kind", [(9000, 16, "spread"), (8300, 16, "clusters"), (4500, 32, "contracted"),
-                                       (4200, 64, "contracted"), (4300, 64, "clusters")])
+                                       (4200, 64, "contracted"), (4300, 64, "clusters"), (4150, 128, "contracted")])
 def test_bf16_full_sweep_route(n, d, kind):
     """BF16 from n = 8,192 (d = 16) or 4,096 (d = 32, 64, 128) on.  When more than half of
     the tiles are flagged (d = 16 from X ~ N(0, 1), any d from a contracted start) the sparse
