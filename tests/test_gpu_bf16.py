@@ -256,3 +256,33 @@ def test_bf16_route_sample_alternating():
             assert loss == first[kind], (what, loss, first[kind])
         first.setdefault(kind, loss)
     G.close()
+
+
+@pytest.mark.parametrize("n,d,kind", [(9000, 16, "spread"), (8300, 16, "clusters"), (4200, 64, "contracted"),
+                                       (4300, 64, "clusters")])
+def test_bf16_reversed_tile_order(n, d, kind):
+    """The BF16 path with its tiles taken in reverse order (GEMPE_F_REVERSE_TILES), on the
+    full matrix-core route (spread at d = 16 through the route sample, contracted at d = 64)
+    and on the list route (clusters): the loss is a fixed-order sum of per-item or per-list
+    slots, so it is bit for bit the forward run's; the gradient (atomics) agrees to rounding."""
+    if kind == "clusters":
+        X, lab = clusters(n, d, 40, spread=0.1, sep=4.0, seed=n)
+        order = np.argsort(lab, kind="stable")
+        X, lab = X[order], lab[order]
+        rng = np.random.default_rng(n)
+        u = rng.integers(0, n, 3 * n)
+        members = [np.nonzero(lab == k)[0] for k in range(40)]
+        g = synth.csr_from_edges(n, u, np.array([rng.choice(members[lab[a]]) for a in u]))
+    else:
+        g = synth.chung_lu(n, 10.0, 2.4, seed=n)
+        scale = 1.5 / np.sqrt(2 * d) if kind == "contracted" else 1.0
+        X = synth.init_embedding(n, d, seed=n + 1, scale=scale)
+    note(f"bf16 reversed tile order n={n} d={d} {kind}")
+    G = gempe.Graph(n, g.row_ptr, g.col_idx)
+    fwd = gpu_loss_grad(G, X, params=gempe.params_default(**BF16))
+    rev = gpu_loss_grad(G, X, params=gempe.params_default(flags=gempe.GEMPE_F_REVERSE_TILES, **BF16))
+    assert rev["loss"] == fwd["loss"], (rev["loss"], fwd["loss"])
+    assert rev["edge_hits"] == fwd["edge_hits"] == g.m
+    A = np.abs(fwd["grad"]).sum(axis=1) + 1e-30
+    assert_grad_close(rev["grad"], fwd["grad"], A, rtol=1e-5, what=f"bf16 reversed n{n} d{d} {kind}")
+    G.close()
