@@ -68,6 +68,16 @@ TRAFFIC_SOURCES = ["paper_2011_03479_amd/csrc/sweep.hip", "paper_2011_03479_amd/
                    "paper_2011_03479_amd/csrc/internal.h"]
 
 
+# the BF16 screen's record hashes its own sources
+SCREEN_SOURCES = ["paper_2011_03479_amd/csrc/gram.hip", "paper_2011_03479_amd/csrc/internal.h",
+                  "paper_2011_03479_amd/csrc/ltab_stage.h", "paper_2011_03479_amd/csrc/pairfn.h",
+                  "paper_2011_03479_amd/csrc/tiles.h"]
+
+
+def sources_of(kernel: str):
+    return SCREEN_SOURCES if "k_gram_screen" in kernel else TRAFFIC_SOURCES
+
+
 def record_traffic(outdir: str, kernel: str, workload: str, copy_bytes: int):
     """Writes profiles/traffic_<workload>.json from four rocprofv3 --pmc runs under
     `outdir` (pmc_fetch, pmc_write: FETCH_SIZE / WRITE_SIZE of the bench; pmc_copy_fetch,
@@ -92,9 +102,9 @@ def record_traffic(outdir: str, kernel: str, workload: str, copy_bytes: int):
     ff = copy_bytes / 1024.0 / cfetch
     wf = copy_bytes / 1024.0 / cwrite
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources_of(kernel):
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    rec = {"kernel": kernel, "workload": workload, "sources": TRAFFIC_SOURCES,
+    rec = {"kernel": kernel, "workload": workload, "sources": sources_of(kernel),
            "source_sha256": h.hexdigest(), "dispatches": nk,
            "fetch_size_kib_per_launch": fetch, "write_size_kib_per_launch": write,
            "copy_probe_bytes": copy_bytes, "copy_fetch_size_kib": cfetch, "copy_write_size_kib": cwrite,
@@ -357,11 +367,13 @@ def attach_traffic(roof, kernel: str, workload: str):
 
 
 def traffic_kernel_of(w):
-    """The symbol of the FP32 workload's dominant kernel, as rocprofv3 names it (the key of its
-    traffic record), or None."""
-    if w.precision != "fp32":
-        return None
+    """The symbol of the workload's dominant kernel, as rocprofv3 names it (the key of its
+    traffic record), or None.  On the BF16 path that is the screen (rocprofv3 reports its
+    name mangled), whose record is attached only while the screen is the roofline's kernel."""
     d, n = w.d, w.graph.n
+    if w.precision == "bf16":
+        rw = 8 if (n + 511) // 512 >= 64 else 2
+        return f"_ZN5gempe13k_gram_screenILi{d}ELi{rw}EEEvPKDF16bPKfS4_iiixfPhiiPKiPi"
     if n <= 23000 and d <= 16:
         return f"gempe::k_iter<{d if d <= 4 else (8 if d <= 8 else 16)}>"
     if d == 16 and n >= 8192:
@@ -374,7 +386,7 @@ def traffic_kernel_of(w):
 def summary(w, r, steps: int, warmup: int):
     roof = roofline_of(w, r, steps)
     kern = traffic_kernel_of(w)
-    if kern is not None:
+    if kern is not None and roof is not None and ("k_gram_screen" in kern) == roof["kernel"].startswith("k_gram_screen"):
         attach_traffic(roof, kern, w.name)
     d = {"workload": w.name, "n": w.graph.n, "m": w.graph.m, "d": w.d, "precision": w.precision,
          "steps": steps, "warmup": warmup, "pairs_per_iter": r["N"], "value": r["value"], "unit": "pairs/s",
